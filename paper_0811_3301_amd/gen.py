@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module only draws numbers: it holds none of the search method's arithmetic
+(no envelope, no bound, no warping distance).  Every generator takes an explicit
+seed tuple and returns float64 arrays; callers cast to float32 for the device.
+
+Workloads (each stands in for a data set of the paper's experiments, Sec. 10):
+
+* ``random_walk``: x_1 = 0 and x_i = x_{i-1} + N(0,1) (Sec. 10.1, also App. B).
+  A series of length n holds the start value and n-1 Gaussian steps.
+* ``shape_signatures``: centroid-distance signatures of random star-shaped
+  polygons, a synthetic stand-in for the shape archives of Sec. 10.2, which are
+  not available here.
+* ``poisson_arrivals``: request arrival times for the serving loop.
+
+Seeds follow ``SeedSequence([8113301, config_id, role, *extra])``, role 0 = database,
+1 = queries, 2 = arrivals and per-request draws.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 8113301
+
+ROLE_DB = 0
+ROLE_QUERY = 1
+ROLE_ARRIVAL = 2
+
+
+def rng(config_id: int, role: int, *extra: int) -> np.random.Generator:
+    """PCG64 generator for (config, role, extra...)."""
+    ss = np.random.SeedSequence([BASE_SEED, int(config_id), int(role), *[int(e) for e in extra]])
+    return np.random.Generator(np.random.PCG64(ss))
+
+
+def random_walk(count: int, n: int, gen: np.random.Generator) -> np.ndarray:
+    """``count`` random walks of length ``n``: first value 0, then cumulative N(0,1) steps."""
+    out = np.zeros((count, n), dtype=np.float64)
+    if n > 1 and count > 0:
+        steps = gen.standard_normal((count, n - 1))
+        np.cumsum(steps, axis=1, out=out[:, 1:])
+    return out
+
+
+def white_noise(count: int, n: int, gen: np.random.Generator) -> np.ndarray:
+    """``count`` series of i.i.d. N(0,1) values (App. B workload)."""
+    return gen.standard_normal((count, n))
+
+
+def _polygon_signature(n: int, gen: np.random.Generator, sigma: float) -> np.ndarray:
+    v = int(gen.integers(5, 13))                      # 5..12 vertices
+    theta = np.sort(gen.uniform(0.0, 2.0 * np.pi, v))
+    r = gen.uniform(0.5, 1.5, v)
+    px, py = r * np.cos(theta), r * np.sin(theta)
+    # area centroid of the closed polygon (shoelace formula)
+    qx, qy = np.roll(px, -1), np.roll(py, -1)
+    cross = px * qy - qx * py
+    area = 0.5 * cross.sum()
+    if abs(area) < 1e-12:
+        cx, cy = px.mean(), py.mean()
+    else:
+        cx = ((px + qx) * cross).sum() / (6.0 * area)
+        cy = ((py + qy) * cross).sum() / (6.0 * area)
+    # n boundary points spaced uniformly in arc length, starting at vertex 0
+    seg = np.hypot(qx - px, qy - py)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    s = np.arange(n) * (cum[-1] / n)
+    k = np.clip(np.searchsorted(cum, s, side="right") - 1, 0, v - 1)
+    t = (s - cum[k]) / np.where(seg[k] > 0, seg[k], 1.0)
+    bx = px[k] + t * (qx[k] - px[k])
+    by = py[k] + t * (qy[k] - py[k])
+    sig = np.hypot(bx - cx, by - cy)
+    # circular Gaussian smoothing (wrap-around), sigma in samples
+    if sigma > 0:
+        half = int(np.ceil(4 * sigma))
+        taps = np.arange(-half, half + 1)
+        kern = np.exp(-0.5 * (taps / sigma) ** 2)
+        kern /= kern.sum()
+        sm = np.zeros(n)
+        for tap, wgt in zip(taps, kern):
+            sm += wgt * np.roll(sig, tap)
+        sig = sm
+    sig = np.roll(sig, int(gen.integers(0, n)))
+    sd = sig.std()
+    return (sig - sig.mean()) / (sd if sd > 0 else 1.0)
+
+
+def shape_signatures(count: int, n: int, gen: np.random.Generator, sigma: float = 4.0) -> np.ndarray:
+    """``count`` z-normalised centroid-distance signatures of random star-shaped polygons."""
+    out = np.empty((count, n), dtype=np.float64)
+    for c in range(count):
+        out[c] = _polygon_signature(n, gen, sigma)
+    return out
+
+
+def poisson_arrivals(rate_qps: float, count: int, gen: np.random.Generator) -> np.ndarray:
+    """Arrival times (seconds from 0) of ``count`` requests of a Poisson process."""
+    return np.cumsum(gen.exponential(1.0 / rate_qps, count))
+
+
+def band_from_fraction(n: int, f: float) -> int:
+    """Half-width w = floor(f*n + 0.5) for a band given as a fraction of the length."""
+    return int(np.floor(f * n + 0.5))
+
+
+# Named workloads: (database size, series length, query count, bands, exponents).
+WORKLOADS = {
+    "rw128_small": dict(config_id=1, N=1000, n=128, Q=16, w=(13,), p=(1,), kind="random_walk"),
+    "rw256": dict(config_id=2, N=100_000, n=256, Q=256, w=(26,), p=(1, 2), kind="random_walk"),
+    "shape512": dict(config_id=3, N=50_000, n=512, Q=512, w=(26, 51), p=(1,), kind="shape"),
+}
+
+
+def make_workload(name: str, N: int | None = None, Q: int | None = None):
+    """Database and queries (float64) of a named workload, optionally truncated to N / Q."""
+    spec = WORKLOADS[name]
+    n = spec["n"]
+    N = spec["N"] if N is None else N
+    Q = spec["Q"] if Q is None else Q
+    if spec["kind"] == "random_walk":
+        db = random_walk(N, n, rng(spec["config_id"], ROLE_DB))
+        qs = random_walk(Q, n, rng(spec["config_id"], ROLE_QUERY))
+    else:
+        db = shape_signatures(N, n, rng(spec["config_id"], ROLE_DB))
+        qs = shape_signatures(Q, n, rng(spec["config_id"], ROLE_QUERY))
+    return db, qs
