@@ -1,0 +1,221 @@
+"""Benchmark: 1-NN search under band-constrained DTW_1 on one MI355X.
+
+Workload (the paper's 256-sample random-walk experiment, Sec. 10.1, at a 100,000-series
+database): N = 100,000 random walks of length n = 256, Q = 256 fresh random-walk queries,
+w = 26 (10% of n), p = 1, 1-NN.  A step is one nn_search call over the whole query batch in
+the two-pass mode (LB_Keogh -> LB_Improved -> DTW); the database and queries are resident in
+HBM before timing.  The same batch is also timed in LB_Keogh-only and brute-force mode, and at
+p = 2.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "1-NN DTW queries/sec (LB_Improved vs LB_Keogh vs brute); LB GB/s; p50/p99"
+VALU_PEAK_OPS = 256 * 64 * 2.4e9      # fp32 VALU lane-instructions per second (unpacked)
+HBM_PEAK_GBPS = 8000.0
+LBK_OPS_PER_ELEM = 3                  # clamp (both comparisons, one med3), subtract, accumulate
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_mode(L, ctx, db, Yd, w, p, mode, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        L.lbimp_nn_search(ctx, db, Yd, w, p, 1, mode, stats=False)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    per = []
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(steps):
+        a = time.perf_counter()
+        L.lbimp_nn_search(ctx, db, Yd, w, p, 1, mode, stats=False)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - a) * 1e3)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    return dict(ms_per_step=ev_ms / steps, wall_ms_per_step=wall * 1e3 / steps, step_ms=per)
+
+
+def stage_profile(L, ctx, db, Yd, w, p, mode, steps):
+    import torch
+    L.lbimp_ctx_set_timing(ctx, True)
+    acc = {}
+    for _ in range(steps):
+        L.lbimp_nn_search(ctx, db, Yd, w, p, 1, mode, stats=False)
+        for k, v in L.lbimp_ctx_stage_times(ctx).items():
+            acc[k] = acc.get(k, 0.0) + v
+    L.lbimp_ctx_set_timing(ctx, False)
+    torch.cuda.synchronize()
+    return {k: v / steps for k, v in acc.items()}
+
+
+def single_query_lb_gbps(L, ctx, steps=20):
+    """LB_Keogh of one query over a 1,000,000 x 128 random-walk database (512 MB, larger than
+    the 256 MB Infinity Cache): the HBM-bound form of the first pass."""
+    import torch
+    from paper_0811_3301_amd import gen
+    N, n, w = 1_000_000, 128, 13
+    g = gen.rng(5, gen.ROLE_DB)
+    X = torch.from_numpy(gen.random_walk(N, n, g).astype(np.float32)).cuda()
+    db = L.Db(ctx, X)
+    del X
+    y = torch.from_numpy(gen.random_walk(1, n, gen.rng(5, gen.ROLE_QUERY)).astype(np.float32)).cuda()
+    U, Lo = L.lbimp_envelope(ctx, y, w)
+    out = torch.empty((1, N), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        L.lbimp_db_lb_keogh(ctx, db, U, Lo, 1, out=out)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        L.lbimp_db_lb_keogh(ctx, db, U, Lo, 1, out=out)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    db.close()
+    nbytes = N * n * 4
+    return dict(db_bytes=nbytes, ms=ms, gbps=nbytes / ms / 1e6, frac_hbm=nbytes / ms / 1e6 / HBM_PEAK_GBPS)
+
+
+def cpu_baseline(X, Ys, w, p, gpu_idx, budget_s=12.0):
+    """The fp64 oracle (brute-force DTW over the whole database) on a bounded sample of queries."""
+    from oracle import native
+    native.load()
+    X64 = X.astype(np.float64)
+    t = time.perf_counter()
+    idx, _ = native.nn_bruteforce(X64, Ys[:1].astype(np.float64), w, p, 1)
+    first = time.perf_counter() - t
+    more = int(max(0, min(Ys.shape[0] - 1, budget_s / max(first, 1e-3) - 1)))
+    t = time.perf_counter()
+    idx2, _ = native.nn_bruteforce(X64, Ys[1:1 + more].astype(np.float64), w, p, 1)
+    rest = time.perf_counter() - t
+    nq = 1 + more
+    total = first + rest
+    allidx = np.concatenate([idx[:, 0], idx2[:, 0]]) if more else idx[:, 0]
+    agree = float(np.mean(allidx == gpu_idx[:nq]))
+    return dict(value=nq / total, unit="queries/s", cores=native.num_threads(), kind="oracle",
+                sample=f"{nq} of {Ys.shape[0]} queries, brute-force fp64 DTW against all {X.shape[0]} candidates",
+                seconds=total, index_agreement=agree)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--quick", action="store_true", help="two-pass mode only (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0811_3301_amd import gen, lbimp as L
+
+    L.load()
+    N, n, Q, w = 100_000, 256, 256, 26
+    log("generating workload")
+    db64, qs64 = gen.make_workload("rw256")
+    X, Ys = db64.astype(np.float32), qs64.astype(np.float32)
+    ctx = L.Ctx(0)
+    db = L.Db(ctx, torch.from_numpy(X).cuda())
+    Yd = torch.from_numpy(Ys).cuda()
+    torch.cuda.synchronize()
+
+    log("timing two-pass p=1")
+    imp = time_mode(L, ctx, db, Yd, w, 1, "improved", args.steps, args.warmup)
+    idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, "improved")
+    gpu_idx = idx.cpu().numpy()[:, 0]
+    stages = stage_profile(L, ctx, db, Yd, w, 1, "improved", max(3, args.steps // 2))
+
+    modes = {"improved": dict(qps=Q / (imp["ms_per_step"] / 1e3), ms_per_step=imp["ms_per_step"])}
+    if not args.quick:
+        for mode, steps in (("keogh", args.steps), ("brute", max(2, args.steps // 10))):
+            log(f"timing {mode} p=1")
+            r = time_mode(L, ctx, db, Yd, w, 1, mode, steps, 1)
+            modes[mode] = dict(qps=Q / (r["ms_per_step"] / 1e3), ms_per_step=r["ms_per_step"])
+            idx_m = L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, mode, stats=False)[0].cpu().numpy()[:, 0]
+            modes[mode]["same_result_as_two_pass"] = bool(np.array_equal(idx_m, gpu_idx))
+        log("timing two-pass p=2")
+        r2 = time_mode(L, ctx, db, Yd, w, 2, "improved", args.steps, 1)
+        rk2 = time_mode(L, ctx, db, Yd, w, 2, "keogh", args.steps, 1)
+        _, _, st2 = L.lbimp_nn_search(ctx, db, Yd, w, 2, 1, "improved")
+        p2 = dict(improved_qps=Q / (r2["ms_per_step"] / 1e3), keogh_qps=Q / (rk2["ms_per_step"] / 1e3),
+                  pruned_keogh=float(st2[:, 2].sum() / (N * Q)), pruned_improved=float(st2[:, 3].sum() / (N * Q)),
+                  dtw_fraction=float(st2[:, 4].sum() / (N * Q)))
+    else:
+        p2 = None
+
+    sweep_ms = stages["lb_keogh"]
+    elems = Q * N * n
+    achieved = LBK_OPS_PER_ELEM * elems / (sweep_ms / 1e3) / 1e12
+    roofline = dict(bound="alu", kernel="k_lbk_sweep (LB_Keogh of every query x candidate)",
+                    achieved=achieved, peak=VALU_PEAK_OPS / 1e12, unit="TOP/s", frac=achieved * 1e12 / VALU_PEAK_OPS,
+                    traffic=None, kernel_ms=sweep_ms, ops_per_element=LBK_OPS_PER_ELEM, elements=elems)
+
+    lbg = None
+    if not args.quick:
+        log("single-query LB_Keogh sweep over a 512 MB database")
+        lbg = single_query_lb_gbps(L, ctx)
+
+    cpu = None
+    if not args.no_cpu:
+        log("oracle CPU baseline")
+        cpu = cpu_baseline(X, Ys, w, 1, gpu_idx)
+
+    step_ms = np.array(imp["step_ms"])
+    out = {
+        "metric": METRIC,
+        "value": modes["improved"]["qps"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": imp["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "random-walk 1-NN, DTW_1, n=256, database 100000, 256 queries per step, w=26, "
+                               "two-pass LB_Keogh->LB_Improved->DTW", "N": N, "n": n, "Q": Q, "w": w, "p": 1, "k": 1},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "modes_p1": modes,
+        "p2": p2,
+        "pruning_p1": dict(pruned_keogh=float(st[:, 2].sum() / (N * Q)),
+                           pruned_improved=float(st[:, 3].sum() / (N * Q)),
+                           dtw_fraction=float(st[:, 4].sum() / (N * Q)),
+                           abandoned_fraction_of_dtw=float(st[:, 5].sum() / max(1, st[:, 4].sum()))),
+        "stage_ms_p1": stages,
+        "lb_single_query_hbm": lbg,
+        "batch_latency_ms": dict(p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99))),
+    }
+    print(json.dumps(out), flush=True)
+    db.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

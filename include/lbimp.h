@@ -1,0 +1,137 @@
+/*
+ * lbimp.h -- C-ABI of the MI355X (gfx950) two-pass DTW nearest-neighbour search.
+ *
+ * Method: Lemire, "Faster Retrieval with a Two-Pass Dynamic-Time-Warping Lower
+ * Bound" (arXiv:0811.3301).  For each query y the library computes the warping
+ * envelope (Sec. 5, Sec. 6), prunes candidates with LB_Keogh (Sec. 7), prunes the
+ * survivors with LB_Improved (Sec. 8), and runs banded DTW_p (Sec. 4) only on what
+ * remains, against a best-so-far threshold (Algorithm 3).
+ *
+ * Conventions shared by every call
+ *   - Series are float32, row-major, equal length n (Sec. 2), 1 <= n <= LBIMP_MAX_LEN.
+ *   - Pointers marked "device" are device memory of the context's GPU; the caller
+ *     owns them and keeps them alive until the work on the context's stream is done.
+ *     The library never frees caller memory.  Pointers marked "host" are host memory.
+ *   - Calls enqueue work on the context's stream and return without waiting, except
+ *     where a host output is written (stats, stage times), which waits for the stream.
+ *   - p is the exponent of DTW_p and of the bounds: 1 or 2 (other values return
+ *     LBIMP_E_UNSUPPORTED).  All distances returned are in root form (DTW_p,
+ *     LB_Keogh_p, LB_Improved_p), computed in float32.
+ *   - w is the locality constraint |i - j| <= w (Sec. 4), w >= 0; w >= n is the
+ *     unconstrained DTW and behaves as w = n - 1.
+ *   - Inputs must be finite; non-finite values give unspecified results.
+ *   - Every call returns an LBIMP_* status; no C++ exception crosses the ABI.
+ *     lbimp_last_error() gives a message for the calling thread's last failure.
+ *   - One context per host thread (a context is not thread-safe).  A database
+ *     handle is read-only after creation and may be shared by contexts of its GPU.
+ */
+#ifndef LBIMP_H
+#define LBIMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBIMP_MAX_LEN 4096
+
+enum {
+    LBIMP_OK = 0,
+    LBIMP_E_INVALID = 1,     /* bad argument: null pointer, n < 1, n > LBIMP_MAX_LEN, w < 0, k < 1, ... */
+    LBIMP_E_NOMEM = 2,       /* device or host allocation failed */
+    LBIMP_E_DEVICE = 3,      /* a HIP runtime call failed */
+    LBIMP_E_UNSUPPORTED = 4  /* valid request outside what is implemented (p other than 1 or 2) */
+};
+
+enum {
+    LBIMP_MODE_BRUTE = 0,    /* DTW of every candidate (the definition) */
+    LBIMP_MODE_KEOGH = 1,    /* Algorithm 2: LB_Keogh pruning, then DTW */
+    LBIMP_MODE_IMPROVED = 2  /* Algorithm 3: LB_Keogh, then LB_Improved, then DTW */
+};
+
+/* Per-query counters of one search.  candidates = seeded + pruned_keogh +
+ * pruned_improved + (dtw_started - seeded).  Seeds are the candidates with the
+ * smallest LB_Keogh whose DTW sets the initial threshold; every later candidate is
+ * pruned against that threshold, so the counts do not depend on thread timing.
+ * dtw_abandoned counts DTWs stopped early once they could no longer win; it may
+ * vary between runs because the best-so-far tightens concurrently. */
+typedef struct {
+    int64_t candidates;
+    int64_t seeded;
+    int64_t pruned_keogh;
+    int64_t pruned_improved;
+    int64_t dtw_started;
+    int64_t dtw_abandoned;
+} lbimp_stats;
+
+typedef struct lbimp_ctx lbimp_ctx;
+typedef struct lbimp_db lbimp_db;
+
+/* Thread-local message describing the calling thread's last failing call ("" if none). */
+const char *lbimp_last_error(void);
+
+/* Create a context on GPU `device`, enqueueing on `hip_stream` (a hipStream_t, NULL for
+ * the default stream).  The context owns its workspace (grown on demand). */
+int lbimp_ctx_create(int device, void *hip_stream, lbimp_ctx **out);
+int lbimp_ctx_set_stream(lbimp_ctx *ctx, void *hip_stream);
+void lbimp_ctx_destroy(lbimp_ctx *ctx);
+
+/* Per-stage timing of lbimp_nn_search with HIP events on the context's stream.
+ * With timing on, lbimp_ctx_stage_times waits for the last search and writes up to
+ * `max` stage durations in milliseconds to host array `ms` (order: envelope, lb_keogh
+ * sweep, seed selection, seed DTW, compaction, lb_improved, dtw, finalize); it returns
+ * the number of stages written, or a negative status. */
+int lbimp_ctx_set_timing(lbimp_ctx *ctx, int enable);
+int lbimp_ctx_stage_times(lbimp_ctx *ctx, float *ms, int max);
+
+/* Device-resident database (the flat file of the paper's Sec. 10, kept in HBM).
+ * `rows` is a device [N][n] float32 array; it is copied (row-major and in the
+ * 64-candidate interleaved layout of the LB_Keogh sweep), so the caller may free it
+ * after the call returns and the stream has run.  N may be 0. */
+int lbimp_db_create(lbimp_ctx *ctx, const float *rows, int64_t N, int32_t n, lbimp_db **out);
+void lbimp_db_destroy(lbimp_db *db);
+int64_t lbimp_db_size(const lbimp_db *db);
+int32_t lbimp_db_length(const lbimp_db *db);
+
+/* Warping envelopes (Sec. 5; computed with a van Herk/Gil-Werman block max/min, the
+ * streaming role of Algorithm 1): U[b][i] = max{y[b][k] : |k-i| <= w}, L = min, windows
+ * cut to [0, n).  y, U, L: device [B][n].  B may be 0. */
+int lbimp_envelope(lbimp_ctx *ctx, const float *y, int64_t B, int32_t n, int32_t w, float *U, float *L);
+
+/* LB_Keogh_p(x_c, y) = ||x_c - H(x_c, y)||_p for every row x_c of device [N][n] x, where
+ * (U, L) is the envelope of y (device [n] each) and H the projection of eq. (H) (Sec. 7).
+ * lb: device [N]. */
+int lbimp_lb_keogh(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, const float *U, const float *L,
+                   int32_t p, float *lb);
+
+/* LB_Keogh over a resident database for Q query envelopes at once (Sec. 7):
+ * U, L device [Q][n]; lb device [Q][N] (row q holds LB_Keogh_p of every candidate). */
+int lbimp_db_lb_keogh(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const float *L, int64_t Q,
+                      int32_t p, float *lb);
+
+/* LB_Improved_p(x_c, y) (Sec. 8): LB_Keogh_p(x_c,y)^p + LB_Keogh_p(y, H(x_c,y))^p, the
+ * second term against the envelope (same w) of the projection x' = H(x_c, y).
+ * x device [N][n]; y, U, L device [n] (U, L the envelope of y with this w); lb device [N]. */
+int lbimp_lb_improved(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, const float *y, const float *U,
+                      const float *L, int32_t w, int32_t p, float *lb);
+
+/* DTW_p(x_c, y) under |i-j| <= w by the Sec. 4 recursion, for every row of device [N][n]
+ * x against device [n] y.  dist: device [N]. */
+int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, int32_t n, int32_t w, int32_t p,
+                   float *dist);
+
+/* k nearest neighbours under DTW_p of each of Q queries (device [Q][n], n equal to the
+ * database's length) in database `db` (Algorithms 2 and 3, generalised to DTW_p and k).
+ * Outputs: idx device [Q][k] int64 and dist device [Q][k] float32, sorted by (distance,
+ * index): ties go to the smaller index.  Slots beyond the database size get idx -1 and
+ * dist +inf.  stats: host [Q] or NULL (non-NULL makes the call wait for the stream).
+ * 1 <= k <= 64.  mode: LBIMP_MODE_*. */
+int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
+                    int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBIMP_H */

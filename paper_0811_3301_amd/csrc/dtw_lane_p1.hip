@@ -1,0 +1,13 @@
+// Instantiations of the lane-per-pair DTW kernel for p = 1, band half-widths 0..kLaneMaxW.
+#include "dtw_lane.h"
+
+namespace lbimp {
+
+hipError_t launch_dtw_lane_p1(int w, int grid, const DtwArgs &a, hipStream_t s) {
+    static const auto table = dtw_lane_table<1>(std::make_integer_sequence<int, kLaneMaxW + 1>{});
+    if (w < 0 || w > kLaneMaxW) return hipErrorInvalidValue;
+    table[w](grid, a, s);
+    return hipGetLastError();
+}
+
+}  // namespace lbimp

@@ -1,0 +1,99 @@
+// Internal declarations shared by the kernel translation units and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbimp.h"
+
+namespace lbimp {
+
+constexpr int kWave = 64;
+constexpr float kInf = __builtin_huge_valf();
+constexpr unsigned long long kNoKey = ~0ull;  // larger than every (distance, index) key
+constexpr size_t kLdsBudget = 65536;          // dynamic LDS per workgroup used by any kernel
+constexpr int kLaneMaxW = 63;                 // widest band (half-width) of the lane-per-pair DTW
+
+// Launch wrappers.  Every pointer is device memory; all launches go to `s`.
+// Each returns hipSuccess or the launch error.
+
+// Copy [B][n] envelopes into rows of stride ldo padded with U = +inf, L = -inf (columns >= n
+// and rows in [B, Bpad)), the layout the LB_Keogh sweep reads.
+hipError_t launch_pad_env(const float *U, const float *L, int64_t B, int64_t Bpad, int n, float *Ud, float *Ld,
+                          int ldo, hipStream_t s);
+
+// Row-major [N][n] -> 64-candidate interleaved tiles [T][n4][64] of float4 (zero padded).
+hipError_t launch_pack(const float *rows, int64_t N, int n, float4 *il, hipStream_t s);
+
+// Envelope of B series (rows of length n) into rows of stride ldo; rows b in [B, Bpad) and
+// columns i in [n, ldo) are filled with U = +inf, L = -inf when ldo > n or Bpad > B.
+hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w, float *U, float *L, int ldo,
+                           hipStream_t s);
+
+// LB_Keogh^p of every interleaved candidate against Q padded envelopes (stride ld4 float4).
+// Writes out[q*ldo + c] for c < N (and +inf for c in [N, ldo) when pad_inf).  root: take the
+// p-th root (public output) instead of leaving the pow-domain value.
+hipError_t launch_lbk_sweep(int p, const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le,
+                            int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root, hipStream_t s);
+
+// Per query: pick S candidates of smallest first-pass sum (approximately the S smallest)
+// into seeds[q][0..S) and set their S1 entries to +inf.  S <= 64, S <= N.
+hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int S, int *seeds, hipStream_t s);
+
+// list[q][*] <- candidates c < N with key(S1[q][c], c) < thr[q]; cnt[q] += number kept.
+hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, const unsigned long long *thr,
+                          int *list, int64_t ldl, int *cnt, hipStream_t s);
+
+// prefix[0] = 0, prefix[q+1] = prefix[q] + ceil(count_q / batch), count_q = cnt[q] or `fixed`.
+hipError_t launch_items_prefix(const int *cnt, int64_t fixed, int64_t Q, int batch, long long *prefix,
+                               hipStream_t s);
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t s);
+hipError_t launch_fill_i32(int *p, int v, int64_t count, hipStream_t s);
+
+// Pair list description for the persistent second-pass and DTW kernels.
+struct PairList {
+    const int *list;     // [Q][ldl] candidate ids, or nullptr for "candidate = position"
+    int64_t ldl;
+    const int *cnt;      // [Q] counts, or nullptr for `fixed` pairs per query
+    int64_t fixed;
+};
+
+struct QueryData {
+    const float *Y;      // [Q][ldy] queries
+    int64_t ldy;
+    const float *U, *L;  // [Q][ldq] envelopes (only the second pass reads them)
+    int64_t ldq;
+};
+
+// Second pass.  S2 = S1[q][c] + sum_i d(y_i, env(H(x_c, y)))^p.  With thr: survivors with
+// key(S2, c) < thr[q] are appended to list2/cnt2.  With out_root: out_root[c] = S2^(1/p)
+// (single query).  prefix: items of `lbi_batch(n, w)` pairs; 0 means the per-lane envelope
+// state of this (n, w) does not fit in LDS.
+int lbi_batch(int n, int w);
+hipError_t launch_lbi(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const float *S1,
+                      int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int grid,
+                      const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
+                      hipStream_t s);
+
+// Banded DTW over a pair list.  best (k = 1): per-query best key, updated by atomicMin and used
+// for early abandoning.  thr/res/rescnt (k > 1): keys below thr[q] are appended to res[q].
+// out_root (single query): out_root[c] = DTW_p.  abandon=false computes every DTW in full.
+int dtw_batch(int n, int w);
+hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const long long *prefix,
+                      int64_t Q, int *ctr, int grid, unsigned long long *best, const unsigned long long *thr,
+                      unsigned long long *res, int64_t ldres, int *rescnt, int *abandoned, float *out_root,
+                      bool abandon, hipStream_t s);
+
+// k-th smallest key of res[q][0..min(rescnt[q], 64)) into thr[q] (kNoKey if fewer than k).
+hipError_t launch_kth_key(const unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k,
+                          unsigned long long *thr, hipStream_t s);
+
+// 1-NN outputs from best keys, or k-NN outputs by selecting the k smallest of res[q].
+hipError_t launch_finalize1(const unsigned long long *best, int64_t Q, int p, int64_t *idx, float *dist,
+                            hipStream_t s);
+hipError_t launch_finalize_k(unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k, int p,
+                             int64_t *idx, float *dist, hipStream_t s);
+
+}  // namespace lbimp

@@ -1,0 +1,423 @@
+// Database layout, warping envelopes, the LB_Keogh sweep, seed selection and compaction.
+//
+// Cited passages (Lemire, arXiv:0811.3301): envelope definition (Sec. 5), LB_Keogh and the
+// projection H (Sec. 7), the first pruning test of Algorithms 2 and 3 (Sec. 7, Sec. 8).
+#include "internal.h"
+
+namespace lbimp {
+
+// ------------------------------------------------------------------ database layout
+// Tile t holds candidates [64t, 64t+64); float4 (t, i4, lane) holds elements 4*i4..4*i4+3 of
+// candidate 64t+lane.  A wave reading one i4 of one tile touches 1 KB of contiguous memory.
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ rows, int64_t N, int n, int n4,
+                                               float4 *__restrict__ il, int64_t total) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int lane = (int)(g & 63);
+    int64_t r = g >> 6;
+    int i4 = (int)(r % n4);
+    int64_t t = r / n4;
+    int64_t c = t * 64 + lane;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (c < N) {
+        const float *x = rows + c * (int64_t)n;
+        for (int k = 0; k < 4; ++k) {
+            int i = i4 * 4 + k;
+            if (i < n) v[k] = x[i];
+        }
+    }
+    il[g] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+hipError_t launch_pack(const float *rows, int64_t N, int n, float4 *il, hipStream_t s) {
+    int n4 = (n + 3) / 4;
+    int64_t T = (N + 63) / 64;
+    int64_t total = T * n4 * 64;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rows, N, n, n4, il, total);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ envelopes (Sec. 5)
+// van Herk / Gil-Werman: with blocks of length K = 2w+1 aligned at 0, every window [s, e]
+// (cut to the series) lies in one block or spans two neighbours.  g = running max/min from
+// the block start, h = running max/min to the block end; the window value is
+// max(h[s], g[e]) across a block boundary, g[e] when s starts its block, h[s] when the
+// window is cut by the series end inside one block.
+__global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, int64_t B, int n, int w,
+                                                   float *__restrict__ U, float *__restrict__ L, int ldo) {
+    extern __shared__ float sm[];
+    int64_t b = blockIdx.x;
+    float *Ub = U + b * (int64_t)ldo;
+    float *Lb = L + b * (int64_t)ldo;
+    if (b >= B) {  // padding rows: an envelope that contains every value
+        for (int i = threadIdx.x; i < ldo; i += blockDim.x) {
+            Ub[i] = kInf;
+            Lb[i] = -kInf;
+        }
+        return;
+    }
+    const float *yb = y + b * (int64_t)n;
+    float *gmax = sm, *gmin = sm + n, *hmax = sm + 2 * n, *hmin = sm + 3 * n;
+    const int K = 2 * w + 1;
+    const int nb = (n + K - 1) / K;
+    for (int blk = threadIdx.x; blk < nb; blk += blockDim.x) {
+        int s = blk * K, e = min(n, s + K);
+        float mx = -kInf, mn = kInf;
+        for (int i = s; i < e; ++i) {
+            float v = yb[i];
+            mx = fmaxf(mx, v);
+            mn = fminf(mn, v);
+            gmax[i] = mx;
+            gmin[i] = mn;
+        }
+        mx = -kInf;
+        mn = kInf;
+        for (int i = e - 1; i >= s; --i) {
+            float v = yb[i];
+            mx = fmaxf(mx, v);
+            mn = fminf(mn, v);
+            hmax[i] = mx;
+            hmin[i] = mn;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int s = max(0, i - w), e = min(n - 1, i + w);
+        int bs = s / K, be = e / K;
+        float u, l;
+        if (bs != be) {
+            u = fmaxf(hmax[s], gmax[e]);
+            l = fminf(hmin[s], gmin[e]);
+        } else if (s == bs * K) {
+            u = gmax[e];
+            l = gmin[e];
+        } else {
+            u = hmax[s];
+            l = hmin[s];
+        }
+        Ub[i] = u;
+        Lb[i] = l;
+    }
+    for (int i = n + threadIdx.x; i < ldo; i += blockDim.x) {
+        Ub[i] = kInf;
+        Lb[i] = -kInf;
+    }
+}
+
+hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w, float *U, float *L, int ldo,
+                           hipStream_t s) {
+    if (Bpad == 0) return hipSuccess;
+    size_t lds = sizeof(float) * 4 * (size_t)n;
+    hipLaunchKernelGGL(k_envelope, dim3((unsigned)Bpad), dim3(256), lds, s, y, B, n, w, U, L, ldo);
+    return hipGetLastError();
+}
+
+__global__ void k_pad_env(const float *__restrict__ U, const float *__restrict__ L, int64_t B, int n,
+                          float *__restrict__ Ud, float *__restrict__ Ld, int ldo, int64_t total) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int64_t b = g / ldo;
+    int i = (int)(g % ldo);
+    bool in = b < B && i < n;
+    Ud[g] = in ? U[b * n + i] : kInf;
+    Ld[g] = in ? L[b * n + i] : -kInf;
+}
+
+hipError_t launch_pad_env(const float *U, const float *L, int64_t B, int64_t Bpad, int n, float *Ud, float *Ld,
+                          int ldo, hipStream_t s) {
+    int64_t total = Bpad * ldo;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_env, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, U, L, B, n, Ud, Ld, ldo,
+                       total);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ LB_Keogh sweep (Sec. 7)
+// d(x, [L, U]) = x - med3(x, L, U): zero inside the envelope, x - U above, x - L below.
+template <int P>
+__device__ __forceinline__ float lb_term(float acc, float x, float l, float u) {
+    float d = x - __builtin_amdgcn_fmed3f(x, l, u);
+    if constexpr (P == 1)
+        return acc + fabsf(d);
+    else
+        return fmaf(d, d, acc);
+}
+
+template <int P>
+__device__ __forceinline__ float root_p(float v) {
+    if constexpr (P == 1)
+        return v;
+    else
+        return sqrtf(v);
+}
+
+// Block = 4 waves; wave -> CPL consecutive tiles (lane = candidate), block.y -> QG queries.
+// The QG envelopes are staged through LDS in chunks of ICH float4 and read as broadcasts;
+// every candidate value is read from HBM once per query group.
+template <int P, int QG, int CPL, bool ROOT>
+__global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il, int64_t T, int64_t N, int n4,
+                                                    const float4 *__restrict__ Ue, const float4 *__restrict__ Le,
+                                                    int ld4, int64_t Q, float *__restrict__ out, int64_t ldo,
+                                                    bool pad_inf) {
+    constexpr int ICH = 32;
+    __shared__ float4 sU[QG][ICH];
+    __shared__ float4 sL[QG][ICH];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wave) * CPL;
+    const int64_t q0 = (int64_t)blockIdx.y * QG;
+    float acc[QG][CPL];
+#pragma unroll
+    for (int a = 0; a < QG; ++a)
+#pragma unroll
+        for (int b = 0; b < CPL; ++b) acc[a][b] = 0.f;
+
+    const float4 *src[CPL];
+    bool tv[CPL];
+#pragma unroll
+    for (int b = 0; b < CPL; ++b) {
+        tv[b] = tile0 + b < T;
+        src[b] = il + ((tv[b] ? tile0 + b : 0) * n4) * 64 + lane;
+    }
+
+    for (int c0 = 0; c0 < n4; c0 += ICH) {
+        const int len = min(ICH, n4 - c0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < QG * ICH; t += 256) {
+            int qq = t / ICH, ii = t % ICH;
+            if (ii < len) {
+                sU[qq][ii] = Ue[(q0 + qq) * ld4 + c0 + ii];
+                sL[qq][ii] = Le[(q0 + qq) * ld4 + c0 + ii];
+            }
+        }
+        __syncthreads();
+        for (int ii = 0; ii < len; ++ii) {
+            float4 xv[CPL];
+#pragma unroll
+            for (int b = 0; b < CPL; ++b) xv[b] = src[b][(int64_t)(c0 + ii) * 64];
+#pragma unroll
+            for (int a = 0; a < QG; ++a) {
+                const float4 u = sU[a][ii], l = sL[a][ii];
+#pragma unroll
+                for (int b = 0; b < CPL; ++b) {
+                    float r = acc[a][b];
+                    r = lb_term<P>(r, xv[b].x, l.x, u.x);
+                    r = lb_term<P>(r, xv[b].y, l.y, u.y);
+                    r = lb_term<P>(r, xv[b].z, l.z, u.z);
+                    r = lb_term<P>(r, xv[b].w, l.w, u.w);
+                    acc[a][b] = r;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < QG; ++a) {
+        const int64_t q = q0 + a;
+        if (q >= Q) continue;
+#pragma unroll
+        for (int b = 0; b < CPL; ++b) {
+            if (!tv[b]) continue;
+            const int64_t c = (tile0 + b) * 64 + lane;
+            if (c < N)
+                out[q * ldo + c] = ROOT ? root_p<P>(acc[a][b]) : acc[a][b];
+            else if (pad_inf && c < ldo)
+                out[q * ldo + c] = kInf;
+        }
+    }
+}
+
+template <int P, int QG, int CPL, bool ROOT>
+static hipError_t sweep_variant(const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le, int ld4,
+                                int64_t Q, float *out, int64_t ldo, bool pad_inf, hipStream_t s) {
+    int64_t T = (N + 63) / 64;
+    dim3 grid((unsigned)((T + 4 * CPL - 1) / (4 * CPL)), (unsigned)((Q + QG - 1) / QG));
+    hipLaunchKernelGGL((k_lbk_sweep<P, QG, CPL, ROOT>), grid, dim3(256), 0, s, il, T, N, n4, Ue, Le, ld4, Q, out,
+                       ldo, pad_inf);
+    return hipGetLastError();
+}
+
+hipError_t launch_lbk_sweep(int p, const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le,
+                            int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root, hipStream_t s) {
+    if (N == 0 || Q == 0) return hipSuccess;
+    // Query-group size: envelopes of QG queries are padded to a multiple of QG by the caller.
+    if (Q == 1) {
+        if (p == 1)
+            return root ? sweep_variant<1, 1, 1, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s)
+                        : sweep_variant<1, 1, 1, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s);
+        return root ? sweep_variant<2, 1, 1, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s)
+                    : sweep_variant<2, 1, 1, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s);
+    }
+    if (p == 1)
+        return root ? sweep_variant<1, 16, 2, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s)
+                    : sweep_variant<1, 16, 2, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s);
+    return root ? sweep_variant<2, 16, 2, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s)
+                : sweep_variant<2, 16, 2, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s);
+}
+
+// ------------------------------------------------------------------ seed selection
+// Threshold seeding: the paper's scan starts from b = inf and tightens b in database order;
+// a parallel pass instead computes the DTW of the candidates with the smallest LB_Keogh first.
+// Each thread keeps its 4 smallest (value, index) keys; the 1024 keys of the block are sorted
+// bitonically in LDS and the first S taken.  Approximate top-S is enough: any threshold that
+// is the DTW of some candidate is a valid (never too small) best-so-far.
+__global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, int64_t ldS, int64_t N, int S,
+                                                       int *__restrict__ seeds) {
+    __shared__ unsigned long long keys[1024];
+    const int64_t q = blockIdx.x;
+    float *row = S1 + q * ldS;
+    unsigned long long top[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
+    for (int64_t c = threadIdx.x; c < N; c += 256) {
+        unsigned long long k = ((unsigned long long)__float_as_uint(row[c]) << 32) | (unsigned long long)c;
+        if (k < top[3]) {
+            top[3] = k;
+#pragma unroll
+            for (int a = 3; a > 0; --a) {
+                if (top[a] < top[a - 1]) {
+                    unsigned long long t = top[a];
+                    top[a] = top[a - 1];
+                    top[a - 1] = t;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) keys[threadIdx.x * 4 + a] = top[a];
+    __syncthreads();
+    for (int size = 2; size <= 1024; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < 512; t += 256) {
+                int i = 2 * t - (t & (stride - 1));
+                int j = i + stride;
+                bool up = (i & size) == 0;
+                unsigned long long a = keys[i], b = keys[j];
+                if ((a > b) == up) {
+                    keys[i] = b;
+                    keys[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int r = threadIdx.x; r < S; r += 256) {
+        unsigned long long k = keys[r];
+        int c = k == kNoKey ? -1 : (int)(k & 0xffffffffu);
+        seeds[q * S + r] = c;
+        if (c >= 0) row[c] = kInf;  // its DTW is computed by the seeding stage
+    }
+}
+
+hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int S, int *seeds, hipStream_t s) {
+    if (Q == 0 || S == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select_seeds, dim3((unsigned)Q), dim3(256), 0, s, S1, ldS, N, S, seeds);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ compaction
+// Strict test of Algorithms 2 and 3 on the (value, index) key: a candidate whose bound key is
+// not below the threshold key can at best tie, and a tie goes to the smaller index.
+// Each wave covers 64*CH candidates: one ballot per chunk, one atomicAdd per wave.
+__global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, int64_t ldS, int64_t N,
+                                                  const unsigned long long *__restrict__ thr, int *__restrict__ list,
+                                                  int64_t ldl, int *__restrict__ cnt) {
+    constexpr int CH = 8;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t q = blockIdx.y;
+    const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64 * CH;
+    const unsigned long long t = thr[q];
+    const float *row = S1 + q * ldS;
+    unsigned long long masks[CH];
+    int total = 0;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        int64_t c = base + ch * 64 + lane;
+        bool keep = false;
+        if (c < N) {
+            unsigned long long k = ((unsigned long long)__float_as_uint(row[c]) << 32) | (unsigned long long)c;
+            keep = k < t;
+        }
+        masks[ch] = __ballot(keep);
+        total += __popcll(masks[ch]);
+    }
+    if (total == 0) return;
+    int pos = 0;
+    if (lane == 0) pos = atomicAdd(&cnt[q], total);
+    pos = __shfl(pos, 0);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int *out = list + q * ldl;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        if ((masks[ch] >> lane) & 1ull) out[pos + __popcll(masks[ch] & below)] = (int)(base + ch * 64 + lane);
+        pos += __popcll(masks[ch]);
+    }
+}
+
+hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, const unsigned long long *thr,
+                          int *list, int64_t ldl, int *cnt, hipStream_t s) {
+    if (N == 0 || Q == 0) return hipSuccess;
+    int64_t per_block = 4 * 64 * 8;
+    dim3 grid((unsigned)((N + per_block - 1) / per_block), (unsigned)Q);
+    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, S1, ldS, N, thr, list, ldl, cnt);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ work-item prefix
+__global__ __launch_bounds__(1024) void k_items_prefix(const int *__restrict__ cnt, int64_t fixed, int64_t Q,
+                                                        int batch, long long *__restrict__ prefix) {
+    __shared__ long long part[1024];
+    __shared__ long long carry;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        prefix[0] = 0;
+    }
+    __syncthreads();
+    for (int64_t q0 = 0; q0 < Q; q0 += 1024) {
+        int64_t q = q0 + threadIdx.x;
+        long long v = 0;
+        if (q < Q) {
+            long long c = cnt ? (long long)cnt[q] : (long long)fixed;
+            v = (c + batch - 1) / batch;
+        }
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            long long add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+            __syncthreads();
+            part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (q < Q) prefix[q + 1] = carry + part[threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += part[1023];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_items_prefix(const int *cnt, int64_t fixed, int64_t Q, int batch, long long *prefix,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_items_prefix, dim3(1), dim3(1024), 0, s, cnt, fixed, Q, batch, prefix);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fills (kernels, not memsets)
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t count) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < count) p[g] = v;
+}
+__global__ void k_fill_i32(int *p, int v, int64_t count) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < count) p[g] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *p, int v, int64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
+}  // namespace lbimp

@@ -1,0 +1,71 @@
+"""C-ABI surface (CPU): the built library loads and exports every function declared in
+include/lbimp.h; the binding covers exactly those; the product path has no CPU fallback."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbimp.h")
+PKG = os.path.join(ROOT, "paper_0811_3301_amd")
+LIB = os.path.join(PKG, "liblbimp.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbimp_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib_path():
+    if not os.path.exists(LIB):
+        from paper_0811_3301_amd import build
+        build.build()
+    return LIB
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lbimp_envelope", "lbimp_lb_keogh", "lbimp_lb_improved", "lbimp_dtw_band", "lbimp_nn_search"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib_path):
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_path], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(lbimp_[a-z_0-9]+)$", out, flags=re.M))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+
+
+def test_library_loads_without_gpu(lib_path):
+    lib = ctypes.CDLL(lib_path)
+    for name in declared_functions():
+        assert getattr(lib, name) is not None
+
+
+def test_binding_signatures_match_header():
+    import importlib
+    spec = importlib.util.spec_from_file_location("lbimp_binding", os.path.join(PKG, "lbimp.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    assert sorted(mod.SIGNATURES) == declared_functions()
+
+
+def test_product_path_never_touches_the_oracle():
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle\b|liboracle|oracle\.c", text, flags=re.M), f
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    import importlib
+    spec = importlib.util.spec_from_file_location("lbimp_binding2", os.path.join(PKG, "lbimp.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with pytest.raises(FileNotFoundError):
+        mod.load(str(tmp_path / "nope.so"))

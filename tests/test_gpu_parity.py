@@ -1,0 +1,327 @@
+"""GPU parity: every C-ABI entry point against the fp64 oracle on the same seeded inputs.
+
+The oracle sees the float32-rounded inputs widened to float64 (what the device sees).
+Distances: |gpu - oracle| <= 1e-5 * max(oracle, 1e-3 * ||x - y||_p) (relative error with a
+floor for values near 0).  Nearest-neighbour indices: equal to the oracle's, unless the
+oracle's distance of the device's pick is within that tolerance of the minimum (a tie).
+Envelopes are exact (max/min of the inputs).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import native
+from oracle import reference as R
+from paper_0811_3301_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0811_3301_amd import lbimp
+    lbimp.load()
+    return lbimp
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.Ctx(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(f32(a))).cuda()
+
+
+def lp_scale(X, y, p):
+    return (np.abs(X - y[None, :]) ** p).sum(axis=1) ** (1.0 / p)
+
+
+def assert_close(gpu, orc, scale, what):
+    gpu, orc, scale = np.asarray(gpu, np.float64), np.asarray(orc, np.float64), np.asarray(scale, np.float64)
+    tol = RTOL * np.maximum(np.abs(orc), 1e-3 * scale) + 1e-30
+    err = np.abs(gpu - orc)
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, f"{what}: {bad.size} mismatches, first {bad[:5]}: gpu {gpu[bad[:5]]} oracle {orc[bad[:5]]}"
+    return float(np.max(err / np.maximum(np.abs(orc), 1e-30))) if orc.size else 0.0
+
+
+def walks(count, n, seed):
+    return f32(gen.random_walk(count, n, gen.rng(500, 0, seed))).astype(np.float64)
+
+
+# ------------------------------------------------------------------ envelopes
+@pytest.mark.parametrize("B,n,w", [(3, 1, 0), (2, 2, 1), (4, 63, 5), (4, 64, 0), (5, 65, 64), (2, 100, 200),
+                                   (3, 257, 26), (2, 1024, 205), (1, 4096, 409)])
+def test_envelope(L, ctx, B, n, w):
+    _say(f"envelope B={B} n={n} w={w}")
+    Y = walks(B, n, n + w)
+    U, Lo = L.lbimp_envelope(ctx, to_dev(Y), w)
+    U, Lo = U.cpu().numpy(), Lo.cpu().numpy()
+    for b in range(B):
+        Uo, Loo = R.envelope_naive(Y[b], R.effective_band(n, w))
+        assert np.array_equal(U[b].astype(np.float64), Uo)
+        assert np.array_equal(Lo[b].astype(np.float64), Loo)
+
+
+# ------------------------------------------------------------------ LB_Keogh
+@pytest.mark.parametrize("N,n", [(1, 1), (63, 7), (64, 128), (65, 131), (1000, 256)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_lb_keogh(L, ctx, N, n, p):
+    _say(f"lb_keogh N={N} n={n} p={p}")
+    X = walks(N, n, 1)
+    y = walks(1, n, 2)[0]
+    w = max(0, n // 10)
+    Uo, Lo = R.envelope_naive(y, w)
+    lb = L.lbimp_lb_keogh(ctx, to_dev(X), to_dev(Uo), to_dev(Lo), p).cpu().numpy()
+    s1, _ = native.lb_many(X, y, w, p)
+    assert_close(lb, s1 ** (1.0 / p), lp_scale(X, y, p), "lb_keogh")
+
+
+@pytest.mark.parametrize("Q", [1, 3, 17])
+@pytest.mark.parametrize("p", [1, 2])
+def test_db_lb_keogh(L, ctx, Q, p):
+    N, n, w = 777, 96, 9
+    _say(f"db_lb_keogh Q={Q} p={p}")
+    X = walks(N, n, 3)
+    Ys = walks(Q, n, 4)
+    db = L.Db(ctx, to_dev(X))
+    env = [R.envelope_naive(Ys[q], w) for q in range(Q)]
+    U = to_dev(np.stack([e[0] for e in env]))
+    Lo = to_dev(np.stack([e[1] for e in env]))
+    lb = L.lbimp_db_lb_keogh(ctx, db, U, Lo, p).cpu().numpy()
+    for q in range(Q):
+        s1, _ = native.lb_many(X, Ys[q], w, p)
+        assert_close(lb[q], s1 ** (1.0 / p), lp_scale(X, Ys[q], p), f"db_lb_keogh q={q}")
+    db.close()
+
+
+# ------------------------------------------------------------------ LB_Improved
+@pytest.mark.parametrize("N,n,w", [(70, 32, 3), (130, 128, 13), (65, 256, 26), (40, 512, 51), (20, 1024, 205),
+                                   (10, 50, 100), (9, 5, 0)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_lb_improved(L, ctx, N, n, w, p):
+    _say(f"lb_improved N={N} n={n} w={w} p={p}")
+    X = walks(N, n, 5)
+    y = walks(1, n, 6)[0]
+    wb = R.effective_band(n, w)
+    Uo, Lo = R.envelope_naive(y, wb)
+    lb = L.lbimp_lb_improved(ctx, to_dev(X), to_dev(y), to_dev(Uo), to_dev(Lo), w, p).cpu().numpy()
+    _, s2 = native.lb_many(X, y, wb, p)
+    assert_close(lb, s2 ** (1.0 / p), lp_scale(X, y, p), "lb_improved")
+
+
+# ------------------------------------------------------------------ DTW
+@pytest.mark.parametrize("N,n,w", [(70, 1, 0), (70, 2, 1), (130, 64, 0), (130, 128, 13), (65, 256, 26),
+                                   (33, 512, 51), (20, 300, 63), (10, 200, 64), (8, 512, 102), (4, 97, 500),
+                                   (3, 1024, 205)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_dtw_band(L, ctx, N, n, w, p):
+    _say(f"dtw_band N={N} n={n} w={w} p={p}")
+    X = walks(N, n, 7)
+    y = walks(1, n, 8)[0]
+    d = L.lbimp_dtw_band(ctx, to_dev(X), to_dev(y), w, p).cpu().numpy()
+    D = native.dtw_pow_many(X, y, R.effective_band(n, w), p)
+    assert_close(d, D ** (1.0 / p), lp_scale(X, y, p), "dtw_band")
+
+
+# ------------------------------------------------------------------ nearest-neighbour search
+def oracle_knn(X, Ys, w, p, k):
+    idx, dist = native.nn_bruteforce(X, Ys, R.effective_band(X.shape[1], w), p, k)
+    return idx, dist
+
+
+def check_knn(X, Ys, w, p, k, gidx, gdist, what):
+    n = X.shape[1]
+    wb = R.effective_band(n, w)
+    for q in range(Ys.shape[0]):
+        D = native.dtw_pow_many(X, Ys[q], wb, p)
+        order = R.key_order(D)
+        want = order[:k]
+        kk = min(k, X.shape[0])
+        scale = lp_scale(X, Ys[q], p)
+        assert np.all(gidx[q, kk:] == -1) and np.all(np.isinf(gdist[q, kk:]))
+        for r in range(kk):
+            c = int(gidx[q, r])
+            dmin = D[want[r]] ** (1.0 / p)
+            if c != want[r]:
+                assert 0 <= c < X.shape[0], (what, q, r, c)
+                dc = D[c] ** (1.0 / p)
+                assert dc <= dmin + RTOL * max(dmin, 1e-3 * scale[c]), (what, q, r, c, int(want[r]), dc, dmin)
+            assert abs(gdist[q, r] - dmin) <= RTOL * max(dmin, 1e-3 * scale[want[r]]) + 1e-30, (what, q, r)
+        assert len(set(gidx[q, :kk].tolist())) == kk
+
+
+def check_stats(X, Ys, w, p, st, mode):
+    """Counts relative to the exact final threshold b*: the device threshold is never below b*,
+    so it prunes no candidate whose bound is below b* (up to float32 rounding)."""
+    N, n = X.shape
+    wb = R.effective_band(n, w)
+    for q in range(Ys.shape[0]):
+        cand, seeded, pk, pi, started, aband = st[q]
+        assert cand == N
+        assert seeded + pk + pi + (started - seeded) == N
+        assert 0 <= aband <= started
+        if mode == "brute":
+            assert started == N and pk == pi == 0
+            continue
+        D = native.dtw_pow_many(X, Ys[q], wb, p)
+        s1, s2 = native.lb_many(X, Ys[q], wb, p)
+        bstar = D.min()
+        slack = 1 + 1e-4
+        assert pk <= np.sum(s1 * slack >= bstar)
+        assert pk + pi <= np.sum(s2 * slack >= bstar)
+        if mode == "keogh":
+            assert pi == 0
+
+
+@pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("k", [1, 5])
+def test_nn_search_small_random_walk(L, ctx, mode, p, k):
+    _say(f"nn_search rw128_small mode={mode} p={p} k={k}")
+    db64, qs64 = gen.make_workload("rw128_small")
+    X, Ys = f32(db64).astype(np.float64), f32(qs64).astype(np.float64)
+    db = L.Db(ctx, to_dev(X))
+    idx, dist, st = L.lbimp_nn_search(ctx, db, to_dev(Ys), 13, p, k, mode)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    check_knn(X, Ys, 13, p, k, idx, dist, f"{mode} p={p} k={k}")
+    check_stats(X, Ys, 13, p, st, mode)
+    if k == 1 and p == 1:
+        # the reported result on the raw float64 data is the same candidate (no tie at this size)
+        oi, _ = oracle_knn(db64, qs64, 13, 1, 1)
+        assert np.mean(oi[:, 0] == idx[:, 0]) >= 0.9
+    db.close()
+
+
+EDGE_CASES = {
+    "N1": dict(N=1, n=16, w=2),
+    "N65": dict(N=65, n=33, w=4),
+    "n1": dict(N=50, n=1, w=0),
+    "n2": dict(N=50, n=2, w=5),
+    "w0": dict(N=300, n=40, w=0),
+    "w_ge_n": dict(N=100, n=30, w=30),
+    "wide_wave_path": dict(N=150, n=256, w=80),
+    "ragged_n": dict(N=200, n=131, w=13),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE_CASES))
+@pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
+def test_nn_search_edge_cases(L, ctx, case, mode):
+    cfg = EDGE_CASES[case]
+    _say(f"nn_search edge {case} mode={mode}")
+    X = walks(cfg["N"], cfg["n"], 11)
+    Ys = walks(5, cfg["n"], 12)
+    db = L.Db(ctx, to_dev(X))
+    for p, k in ((1, 1), (2, 3)):
+        idx, dist, st = L.lbimp_nn_search(ctx, db, to_dev(Ys), cfg["w"], p, k, mode)
+        check_knn(X, Ys, cfg["w"], p, k, idx.cpu().numpy(), dist.cpu().numpy(), f"{case} {mode} p={p} k={k}")
+        check_stats(X, Ys, cfg["w"], p, st, mode)
+    db.close()
+
+
+@pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
+def test_nn_search_ties_constant_and_negative(L, ctx, mode):
+    _say(f"nn_search ties mode={mode}")
+    g = np.random.default_rng(21)
+    n = 48
+    X = f32(np.cumsum(g.standard_normal((90, n)), axis=1) - 5.0).astype(np.float64)
+    X[40] = X[7]          # exact duplicates: the smaller index must win
+    X[77] = X[7]
+    X[12] = -3.0          # constant series
+    X[13] = -3.0
+    Ys = np.stack([X[7], X[12], f32(X[30] + 0.25).astype(np.float64)])
+    db = L.Db(ctx, to_dev(X))
+    idx, dist, st = L.lbimp_nn_search(ctx, db, to_dev(Ys), 5, 1, 3, mode)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    assert list(idx[0]) == [7, 40, 77] and np.all(dist[0] == 0)
+    assert list(idx[1][:2]) == [12, 13]
+    check_knn(X, Ys, 5, 1, 3, idx, dist, f"ties {mode}")
+    db.close()
+
+
+def test_nn_search_empty_database_and_k_above_n(L, ctx):
+    _say("nn_search empty database, k > N")
+    Ys = walks(3, 20, 13)
+    db = L.Db(ctx, torch.empty((0, 20), dtype=torch.float32, device="cuda"))
+    idx, dist, st = L.lbimp_nn_search(ctx, db, to_dev(Ys), 2, 1, 2, "improved")
+    assert np.all(idx.cpu().numpy() == -1) and np.all(np.isinf(dist.cpu().numpy()))
+    db.close()
+    X = walks(3, 20, 14)
+    db = L.Db(ctx, to_dev(X))
+    for mode in ("brute", "keogh", "improved"):
+        idx, dist, st = L.lbimp_nn_search(ctx, db, to_dev(Ys), 2, 1, 5, mode)
+        check_knn(X, Ys, 2, 1, 5, idx.cpu().numpy(), dist.cpu().numpy(), f"k>N {mode}")
+    db.close()
+
+
+def test_invalid_arguments_return_status(L, ctx):
+    _say("invalid arguments")
+    X = to_dev(walks(10, 16, 15))
+    y = to_dev(walks(1, 16, 16)[0])
+    with pytest.raises(L.LbimpError) as e:
+        L.lbimp_dtw_band(ctx, X, y, -1, 1)
+    assert e.value.code == L.LBIMP_E_INVALID
+    with pytest.raises(L.LbimpError) as e:
+        L.lbimp_dtw_band(ctx, X, y, 2, 3)
+    assert e.value.code == L.LBIMP_E_UNSUPPORTED
+    db = L.Db(ctx, X)
+    with pytest.raises(L.LbimpError) as e:
+        L.lbimp_nn_search(ctx, db, to_dev(walks(2, 16, 17)), 2, 1, 65, "improved")
+    assert e.value.code == L.LBIMP_E_INVALID
+    db.close()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_nn_search_rw256_full_size_sampled(L, ctx, p):
+    """The benchmarked workload (100,000 x 256 random walks, 256 queries, w = 26) in the launch
+    configuration the benchmark times; sampled queries against the oracle, all queries across modes."""
+    _say(f"nn_search rw256 full size p={p}")
+    db64, qs64 = gen.make_workload("rw256")
+    X, Ys = f32(db64), f32(qs64)
+    db = L.Db(ctx, to_dev(X))
+    Yd = to_dev(Ys)
+    res = {}
+    for mode in ("improved", "keogh", "brute"):
+        _say(f"  mode {mode}")
+        res[mode] = L.lbimp_nn_search(ctx, db, Yd, 26, p, 1, mode)
+    idx = {m: r[0].cpu().numpy()[:, 0] for m, r in res.items()}
+    dist = {m: r[1].cpu().numpy()[:, 0] for m, r in res.items()}
+    assert np.array_equal(idx["improved"], idx["keogh"])
+    assert np.array_equal(idx["improved"], idx["brute"])
+    assert np.allclose(dist["improved"], dist["brute"], rtol=0, atol=0)
+    sample = [0, 37, 101, 170, 255]
+    X64 = X.astype(np.float64)
+    Y64 = Ys[sample].astype(np.float64)
+    check_knn(X64, Y64, 26, p, 1, idx["improved"][sample, None], dist["improved"][sample, None], "rw256")
+    st = res["improved"][2]
+    assert np.all(st[:, 0] == 100_000)
+    # the second pass prunes something on this workload (the point of the method)
+    assert st[:, 3].sum() > 0 and st[:, 4].mean() < 0.05 * 100_000
+    db.close()
+
+
+def test_nn_search_counts_are_deterministic(L, ctx):
+    _say("determinism of results and pruning counts")
+    X = walks(3000, 64, 18)
+    Ys = walks(20, 64, 19)
+    db = L.Db(ctx, to_dev(X))
+    a = L.lbimp_nn_search(ctx, db, to_dev(Ys), 6, 1, 1, "improved")
+    b = L.lbimp_nn_search(ctx, db, to_dev(Ys), 6, 1, 1, "improved")
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert np.array_equal(a[2][:, :5], b[2][:, :5])
+    db.close()
