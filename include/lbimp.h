@@ -77,6 +77,16 @@ int lbimp_ctx_create(int device, void *hip_stream, lbimp_ctx **out);
 int lbimp_ctx_set_stream(lbimp_ctx *ctx, void *hip_stream);
 void lbimp_ctx_destroy(lbimp_ctx *ctx);
 
+/* Tuning options of a context (they change speed, never results):
+ *   "seeds"         1..64 (default 32): candidates of smallest LB_Keogh whose DTW sets the
+ *                   initial threshold of lbimp_nn_search (at least k are used);
+ *   "lbi_pipeline"  0/1 (default 1): software-pipelined loads in the LB_Improved pass;
+ *   "dtw_group_per_pair"  0/1 (default 0): lbimp_dtw_band computes each DTW with a group of
+ *                   lanes along anti-diagonals (the kernel of the seeding stage) instead of
+ *                   one lane per pair; bands with w > 63 always use the anti-diagonal kernel.
+ * Returns LBIMP_E_INVALID for an unknown name or an out-of-range value. */
+int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
+
 /* Per-stage timing of lbimp_nn_search with HIP events on the context's stream.
  * With timing on, lbimp_ctx_stage_times waits for the last search and writes up to
  * `max` stage durations in milliseconds to host array `ms` (order: envelope, lb_keogh

@@ -68,6 +68,9 @@ struct lbimp_ctx {
     size_t ws_cap = 0;
     bool timing = false;
     bool timed_valid = false;
+    int seeds = 32;             // option "seeds"
+    bool lbi_pipeline = true;   // option "lbi_pipeline"
+    bool dtw_low_latency = false;  // option "dtw_group_per_pair" (lbimp_dtw_band only)
     hipEvent_t ev[kStages + 1] = {};
 };
 
@@ -79,7 +82,7 @@ struct lbimp_db {
     float4 *il = nullptr;   // interleaved tiles for the LB_Keogh sweep
 };
 
-static int persistent_grid(const lbimp_ctx *ctx) { return std::max(1, ctx->num_cu * 8); }
+static int persistent_grid(const lbimp_ctx *ctx) { return std::max(1, ctx->num_cu); }  // CUs; kernels size by occupancy
 
 static int reserve(lbimp_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->ws_cap) return LBIMP_OK;
@@ -162,6 +165,21 @@ int lbimp_ctx_set_timing(lbimp_ctx *ctx, int enable) {
         for (auto &e : ctx->ev) HIPTRY(hipEventCreate(&e));
     ctx->timing = enable != 0;
     ctx->timed_valid = false;
+    return LBIMP_OK;
+}
+
+int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
+    if (!ctx || !name) return fail(LBIMP_E_INVALID, "null argument");
+    if (!strcmp(name, "seeds")) {
+        if (value < 1 || value > kMaxSeeds) return fail(LBIMP_E_INVALID, "seeds must be in [1, %d]", kMaxSeeds);
+        ctx->seeds = (int)value;
+    } else if (!strcmp(name, "lbi_pipeline")) {
+        ctx->lbi_pipeline = value != 0;
+    } else if (!strcmp(name, "dtw_group_per_pair")) {
+        ctx->dtw_low_latency = value != 0;
+    } else {
+        return fail(LBIMP_E_INVALID, "unknown option '%s'", name);
+    }
     return LBIMP_OK;
 }
 
@@ -253,7 +271,7 @@ int lbimp_lb_keogh(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, const f
     HIPTRY(launch_pack(x, N, n, il, ctx->stream));
     HIPTRY(launch_pad_env(U, L, 1, 1, n, Ud, Ld, n4 * 4, ctx->stream));
     HIPTRY(launch_lbk_sweep(p, il, N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4, 1, lb,
-                            N, false, true, ctx->stream));
+                            N, false, true, nullptr, ctx->stream));
     return LBIMP_OK;
 }
 
@@ -275,7 +293,7 @@ int lbimp_db_lb_keogh(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const 
     float *Ld = c2.take<float>((size_t)Qp * n4 * 4);
     HIPTRY(launch_pad_env(U, L, Q, Qp, n, Ud, Ld, n4 * 4, ctx->stream));
     HIPTRY(launch_lbk_sweep(p, db->il, db->N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4,
-                            Q, lb, db->N, false, true, ctx->stream));
+                            Q, lb, db->N, false, true, nullptr, ctx->stream));
     return LBIMP_OK;
 }
 
@@ -309,13 +327,13 @@ int lbimp_lb_improved(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, cons
     HIPTRY(launch_pack(x, N, n, il, s));
     HIPTRY(launch_pad_env(U, L, 1, 1, n, Ud, Ld, n4 * 4, s));
     HIPTRY(launch_lbk_sweep(p, il, N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4, 1, S1,
-                            N, false, false, s));
+                            N, false, false, nullptr, s));
     HIPTRY(launch_fill_i32(ctr, 0, 1, s));
     HIPTRY(launch_items_prefix(nullptr, N, 1, WL, prefix, s));
     QueryData qd{y, n, U, L, n};
     PairList pl{nullptr, 0, nullptr, N};
-    HIPTRY(launch_lbi(p, x, n, wb, qd, pl, S1, N, prefix, 1, ctr, persistent_grid(ctx), nullptr, nullptr, 0,
-                      nullptr, lb, s));
+    HIPTRY(launch_lbi(p, x, (int64_t)N * n * 4, n, wb, qd, pl, S1, N, prefix, 1, ctr, persistent_grid(ctx), nullptr, nullptr, 0,
+                      nullptr, lb, ctx->lbi_pipeline, s));
     return LBIMP_OK;
 }
 
@@ -329,17 +347,22 @@ int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, in
     Carver cv{nullptr};
     cv.take<long long>(2);
     cv.take<int>(1);
+    cv.take<u64>(1);
     if (int r = reserve(ctx, cv.off)) return r;
     Carver c2{static_cast<char *>(ctx->ws)};
     long long *prefix = c2.take<long long>(2);
     int *ctr = c2.take<int>(1);
+    u64 *nothr = c2.take<u64>(1);
     hipStream_t s = ctx->stream;
     HIPTRY(launch_fill_i32(ctr, 0, 1, s));
-    HIPTRY(launch_items_prefix(nullptr, N, 1, dtw_batch(n, wb), prefix, s));
+    HIPTRY(launch_fill_u64(nothr, kNoKey, 1, s));
+    const bool ll = ctx->dtw_low_latency;
+    HIPTRY(launch_items_prefix(nullptr, N, 1, dtw_batch(n, wb, ll), prefix, s));
     QueryData qd{y, n, nullptr, nullptr, 0};
     PairList pl{nullptr, 0, nullptr, N};
-    HIPTRY(launch_dtw(p, x, n, wb, qd, pl, prefix, 1, ctr, persistent_grid(ctx), nullptr, nullptr, nullptr, 0,
-                      nullptr, nullptr, dist, false, s));
+    // no threshold: nothing is abandoned and nothing appended (out_root receives every distance)
+    HIPTRY(launch_dtw(p, x, n, wb, qd, pl, prefix, 1, ctr, persistent_grid(ctx), nullptr, nothr, nullptr, 0,
+                      nullptr, nullptr, dist, false, ll, s));
     return LBIMP_OK;
 }
 
@@ -361,7 +384,7 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     const int64_t Qp = (Q + kQueryGroup - 1) / kQueryGroup * kQueryGroup;
     const bool brute = mode == LBIMP_MODE_BRUTE;
     const bool improved = mode == LBIMP_MODE_IMPROVED;
-    const int S = brute ? 0 : (int)std::min<int64_t>(kMaxSeeds, N);
+    const int S = brute ? 0 : (int)std::min<int64_t>(std::max(ctx->seeds, k), N);
     const int WL = improved ? lbi_batch(n, wb) : 1;
     if (improved && WL == 0)
         return fail(LBIMP_E_UNSUPPORTED, "LB_Improved state for n = %d, w = %d exceeds LDS", n, wb);
@@ -386,8 +409,11 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     }
 
     // ---- workspace layout
+    // Seeds come from the per-wave minima of the sweep once there are enough of them.
+    const int64_t nw = sweep_waves(N, Q);
+    const bool seeds_from_minima = !brute && nw >= 4 * (int64_t)kMaxSeeds;
     auto layout = [&](Carver &c, float *&Ue, float *&Le, float *&S1, int *&seeds, u64 *&best, u64 *&thr, u64 *&res,
-                      int *&list1, int *&list2, int *&counters, long long *&prefix) {
+                      int *&list1, int *&list2, int *&counters, long long *&prefix, u64 *&wmin) {
         Ue = c.take<float>((size_t)Qp * ldq);
         Le = c.take<float>((size_t)Qp * ldq);
         S1 = brute ? nullptr : c.take<float>((size_t)Q * Np);
@@ -399,21 +425,22 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
         list2 = improved ? c.take<int>((size_t)Q * N) : nullptr;
         counters = c.take<int>((size_t)Q * 4 + 8);  // cnt1, cnt2, rescnt, abandoned, item counters
         prefix = c.take<long long>((size_t)Q + 1);
+        wmin = seeds_from_minima ? c.take<u64>((size_t)Q * nw) : nullptr;
     };
     float *Ue, *Le, *S1;
     int *seeds, *list1, *list2, *counters;
-    u64 *best, *thr, *res;
+    u64 *best, *thr, *res, *wmin;
     long long *prefix;
     {
         Carver cv{nullptr};
-        layout(cv, Ue, Le, S1, seeds, best, thr, res, list1, list2, counters, prefix);
+        layout(cv, Ue, Le, S1, seeds, best, thr, res, list1, list2, counters, prefix, wmin);
         if (int r = reserve(ctx, cv.off)) return r;
         Carver c2{static_cast<char *>(ctx->ws)};
-        layout(c2, Ue, Le, S1, seeds, best, thr, res, list1, list2, counters, prefix);
+        layout(c2, Ue, Le, S1, seeds, best, thr, res, list1, list2, counters, prefix, wmin);
     }
     int *cnt1 = counters, *cnt2 = counters + Q, *rescnt = counters + 2 * Q, *abandoned = counters + 3 * Q;
     int *ctr = counters + 4 * Q;
-    const int grid = persistent_grid(ctx);
+    const int grid = persistent_grid(ctx);  // compute units: each persistent kernel sizes its grid by occupancy
     const u64 *T = k == 1 ? best : thr;  // pruning threshold keys of the two passes
     QueryData qd{queries, n, Ue, Le, ldq};
 
@@ -428,21 +455,23 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     if (brute) {
         for (int i = 2; i <= 5; ++i) stage_mark(ctx, i);
         stage_mark(ctx, 6);
-        HIPTRY(launch_items_prefix(nullptr, N, Q, dtw_batch(n, wb), prefix, s));
+        HIPTRY(launch_items_prefix(nullptr, N, Q, dtw_batch(n, wb, false), prefix, s));
         PairList all{nullptr, 0, nullptr, N};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, all, prefix, Q, ctr + 0, grid, k == 1 ? best : nullptr,
-                          k == 1 ? nullptr : thr, res, ldres, rescnt, nullptr, nullptr, false, s));
+                          k == 1 ? nullptr : thr, res, ldres, rescnt, nullptr, nullptr, false, false, s));
     } else {
         // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
         HIPTRY(launch_lbk_sweep(p, db->il, N, n4, reinterpret_cast<float4 *>(Ue), reinterpret_cast<float4 *>(Le),
-                                n4, Q, S1, Np, true, false, s));
+                                n4, Q, S1, Np, true, false, wmin, s));
         stage_mark(ctx, 2);
-        HIPTRY(launch_select_seeds(S1, Np, N, Q, S, seeds, s));
+        HIPTRY(launch_select_seeds(S1, Np, N, Q, S, wmin, nw, seeds, s));
         stage_mark(ctx, 3);
-        HIPTRY(launch_items_prefix(nullptr, S, Q, dtw_batch(n, wb), prefix, s));
+        // Seeds: few pairs per query on the critical path, so a group of lanes per pair (low
+        // latency); they run to completion, their DTWs finishing together.
+        HIPTRY(launch_items_prefix(nullptr, S, Q, dtw_batch(n, wb, true), prefix, s));
         PairList sp{seeds, S, nullptr, S};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, sp, prefix, Q, ctr + 0, grid, k == 1 ? best : nullptr,
-                          k == 1 ? nullptr : thr, res, ldres, rescnt, abandoned, nullptr, k == 1, s));
+                          k == 1 ? nullptr : thr, res, ldres, rescnt, abandoned, nullptr, false, true, s));
         if (k > 1) HIPTRY(launch_kth_key(res, ldres, rescnt, Q, k, thr, s));
         stage_mark(ctx, 4);
         HIPTRY(launch_compact(S1, Np, N, Q, T, list1, N, cnt1, s));
@@ -450,14 +479,14 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
         PairList dl{list1, N, cnt1, 0};
         if (improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
             HIPTRY(launch_items_prefix(cnt1, 0, Q, WL, prefix, s));
-            HIPTRY(launch_lbi(p, db->rows, n, wb, qd, dl, S1, Np, prefix, Q, ctr + 1, grid, T, list2, N, cnt2,
-                              nullptr, s));
+            HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, S1, Np, prefix, Q, ctr + 1, grid, T,
+                              list2, N, cnt2, nullptr, ctx->lbi_pipeline, s));
             dl = PairList{list2, N, cnt2, 0};
         }
         stage_mark(ctx, 6);
-        HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb), prefix, s));
+        HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, false), prefix, s));
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, prefix, Q, ctr + 2, grid, k == 1 ? best : nullptr,
-                          k == 1 ? nullptr : thr, res, ldres, rescnt, abandoned, nullptr, true, s));
+                          k == 1 ? nullptr : thr, res, ldres, rescnt, abandoned, nullptr, true, false, s));
     }
     stage_mark(ctx, 7);
     if (k == 1)

@@ -19,28 +19,50 @@ __device__ __forceinline__ float root_p(float v) {
         return sqrtf(v);
 }
 
-// Persistent work loop: a wave takes the next item from a device counter and maps it to
-// (query, batch) by binary search over the per-query item prefix.  Every wave leaves the
-// loop once the counter passes the total, so the grid always drains.
-__device__ __forceinline__ bool next_item(int *ctr, const long long *__restrict__ prefix, int64_t Q, int64_t &q,
-                                          long long &b) {
-    int item = 0;
-    if ((threadIdx.x & 63) == 0) item = atomicAdd(ctr, 1);
-    item = __shfl(item, 0);
-    const long long total = prefix[Q];
-    if (item >= total) return false;
-    int64_t lo = 0, hi = Q;  // largest q with prefix[q] <= item
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (prefix[mid] <= item)
-            lo = mid;
-        else
-            hi = mid;
+// Persistent work loop.  Items (a query and a batch of its pairs) are dealt to the one-wave
+// blocks of the grid in a fixed stride -- block g takes items g, g + grid, g + 2*grid, ... --
+// so no shared counter is contended.  With a fixed pair count per query the item maps to its
+// query arithmetically; otherwise by binary search over the per-query item prefix.  Every
+// block leaves the loop once its next item is past the total, so the grid always drains.
+struct ItemCursor {
+    long long next, stride, total;
+    long long ipq;  // items per query when every query has the same pair count, else 0
+    const long long *prefix;
+    int64_t Q;
+
+    __device__ ItemCursor(const PairList &pl, const long long *prefix_, int64_t Q_, int batch)
+        : next(blockIdx.x), stride(gridDim.x), prefix(prefix_), Q(Q_) {
+        if (!pl.cnt) {
+            ipq = (pl.fixed + batch - 1) / batch;
+            total = Q * ipq;
+        } else {
+            ipq = 0;
+            total = prefix[Q];
+        }
     }
-    q = lo;
-    b = item - prefix[lo];
-    return true;
-}
+
+    __device__ bool get(int64_t &q, long long &b) {
+        if (next >= total) return false;
+        const long long item = next;
+        next += stride;
+        if (ipq) {
+            q = item / ipq;
+            b = item - q * ipq;
+            return true;
+        }
+        int64_t lo = 0, hi = Q;  // largest q with prefix[q] <= item
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (prefix[mid] <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        q = lo;
+        b = item - prefix[lo];
+        return true;
+    }
+};
 
 __device__ __forceinline__ int pair_count(const PairList &pl, int64_t q) {
     return pl.cnt ? pl.cnt[q] : (int)pl.fixed;
@@ -62,7 +84,7 @@ __device__ __forceinline__ void publish(bool active, float d, int c, int64_t q, 
     if (best) {
         if (key < __hip_atomic_load(&best[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&best[q], key);
     }
-    if (thr && key < thr[q]) {
+    if (thr && res && key < thr[q]) {
         int pos = atomicAdd(&rescnt[q], 1);
         res[q * ldres + pos] = key;
     }
@@ -74,6 +96,37 @@ __device__ __forceinline__ u64 current_threshold(int64_t q, const u64 *best, con
     return kNoKey;
 }
 
+
+// Copy `count` values into LDS with one wave: dst[t] = value_at(t).  Eight loads per lane are
+// issued before any store, so a staging pass costs a few memory latencies, not one per value.
+template <class F>
+__device__ __forceinline__ void stage_lds(float *dst, int count, F value_at) {
+    const int lane = threadIdx.x & 63;
+    for (int base = 0; base < count; base += 64 * 8) {
+        float v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int t = base + r * 64 + lane;
+            v[r] = t < count ? value_at(t) : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int t = base + r * 64 + lane;
+            if (t < count) dst[t] = v[r];
+        }
+    }
+}
+
+// Grid of a persistent kernel: as many one-wave blocks as fit on the chip at once.
+template <class Kernel>
+inline int persistent_grid(Kernel k, size_t lds, int num_cu) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64, lds) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 4;
+    }
+    return num_cu * per_cu;
+}
 
 // Arguments of the lane-per-pair DTW kernels (one instantiation per band half-width).
 struct DtwArgs {
@@ -92,9 +145,37 @@ struct DtwArgs {
     int *abandoned;
     float *out_root;
     bool abandon;
+    const u64 *tkeys;  // [Q] abandon thresholds: best (k = 1) or thr (k > 1); always a valid array
 };
 
-hipError_t launch_dtw_lane_p1(int w, int grid, const DtwArgs &a, hipStream_t s);
-hipError_t launch_dtw_lane_p2(int w, int grid, const DtwArgs &a, hipStream_t s);
+// Arguments of the register-state LB_Improved kernels (one instantiation per half-width).
+struct LbiArgs {
+    const float *rows;
+    int64_t db_bytes;  // size of rows in bytes
+    int n;
+    QueryData qd;
+    PairList pl;
+    const float *S1;
+    int64_t ldS;
+    const long long *prefix;
+    int64_t Q;
+    int *ctr;
+    const u64 *thr;
+    int *list2;
+    int64_t ldl2;
+    int *cnt2;
+    float *out_root;
+    bool pipeline;  // software-pipelined staging (more registers, fewer exposed load latencies)
+};
+
+hipError_t launch_lbi_reg_p1(int w, int num_cu, const LbiArgs &a, hipStream_t s);
+hipError_t launch_lbi_reg_p2(int w, int num_cu, const LbiArgs &a, hipStream_t s);
+
+// Group-of-lanes-per-pair DTW (anti-diagonals in registers); batch = dtw_wave_batch(n, w).
+int dtw_wave_batch(int n, int w);
+hipError_t launch_dtw_wavereg(int p, int w, int num_cu, const DtwArgs &a, hipStream_t s);
+
+hipError_t launch_dtw_lane_p1(int w, int num_cu, const DtwArgs &a, hipStream_t s);
+hipError_t launch_dtw_lane_p2(int w, int num_cu, const DtwArgs &a, hipStream_t s);
 
 }  // namespace lbimp

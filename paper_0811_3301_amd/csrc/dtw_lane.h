@@ -22,15 +22,36 @@ namespace lbimp {
 template <int P, int W>
 __device__ __forceinline__ void dtw_row(float (&D)[2 * W + 1], float xi, const float *yrow) {
     constexpr int BW = 2 * W + 1;
-    float left = kInf;
 #pragma unroll
     for (int k = 0; k < BW; ++k) {
         const float d = xi - yrow[k];
         const float up = (k + 1 < BW) ? D[k + 1] : kInf;
+        const float left = (k > 0) ? D[k - 1] : kInf;
         const float m = __builtin_fminf(__builtin_fminf(D[k], up), left);
-        const float v = (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
-        D[k] = v;
-        left = v;
+        D[k] = (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
+    }
+}
+
+// Four rows at once in skewed order: step s updates cell k = s - r of row r, rows ascending.
+// The in-place reads are unchanged -- when (r, k) runs, D[k] and D[k+1] still hold row r-1
+// and D[k-1] already holds row r -- but the four dependency chains interleave, which hides
+// the latency of the serial left-to-right chain of each row.
+template <int P, int W>
+__device__ __forceinline__ void dtw_rows4(float (&D)[2 * W + 1], const float (&xs)[4], const float *yrow0) {
+    constexpr int BW = 2 * W + 1;
+#pragma unroll
+    for (int s = 0; s < BW + 3; ++s) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = s - r;
+            if (k >= 0 && k < BW) {
+                const float d = xs[r] - yrow0[r + k];
+                const float up = (k + 1 < BW) ? D[k + 1] : kInf;
+                const float left = (k > 0) ? D[k - 1] : kInf;
+                const float m = __builtin_fminf(__builtin_fminf(D[k], up), left);
+                D[k] = (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
+            }
+        }
     }
 }
 
@@ -44,20 +65,22 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
     int64_t cur_q = -1;
     int64_t q;
     long long b;
-    while (next_item(a.ctr, a.prefix, a.Q, q, b)) {
+    ItemCursor items(a.pl, a.prefix, a.Q, 64);
+    while (items.get(q, b)) {
         if (q != cur_q) {
             __syncthreads();
             const float *y = a.qd.Y + q * a.qd.ldy;
-            for (int t = lane; t < plen; t += 64) {
+            stage_lds(ypad, plen, [&](int t) {
                 const int j = t - W;
-                ypad[t] = (j >= 0 && j < n) ? y[j] : kInf;
-            }
+                return (j >= 0 && j < n) ? y[j] : kInf;
+            });
             __syncthreads();
             cur_q = q;
         }
         const long long jj = b * 64 + lane;
-        bool active = jj < pair_count(a.pl, q);
-        const int c = active ? pair_cand(a.pl, q, jj) : 0;
+        const int cl = jj < pair_count(a.pl, q) ? pair_cand(a.pl, q, jj) : -1;
+        bool active = cl >= 0;
+        const int c = active ? cl : 0;
         const float *x = a.rows + (int64_t)c * n;
         float D[BW];
 #pragma unroll
@@ -70,23 +93,28 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
             for (int r = 0; r < 4; ++r) xs[r] = x[r];
         }
         int i0 = 0;
+        // The threshold used after each 4-row group is loaded one group ahead, from one pointer
+        // with no branch around the load, so the wait for it lands where it is used.
+        const u64 *tq = a.tkeys + q;
+        u64 tcur = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (; i0 < nfull; i0 += 4) {
             float xn[4];
             const int inext = i0 + 4 < nfull ? i0 + 4 : i0;  // prefetch the next 4 rows
 #pragma unroll
             for (int r = 0; r < 4; ++r) xn[r] = x[inext + r];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dtw_row<P, W>(D, xs[r], ypad + i0 + r);
+            const u64 tnext = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            dtw_rows4<P, W>(D, xs, ypad + i0);
 #pragma unroll
             for (int r = 0; r < 4; ++r) xs[r] = xn[r];
             if (a.abandon) {
                 float mn = D[0];
 #pragma unroll
                 for (int k = 1; k < BW; ++k) mn = fminf(mn, D[k]);
-                if (active && make_key(mn, c) >= current_threshold(q, a.best, a.thr)) {
+                if (active && make_key(mn, c) >= tcur) {
                     active = false;
                     ++stopped;
                 }
+                tcur = tnext;
                 if (!__any(active)) break;
             }
         }
@@ -101,9 +129,10 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
 }
 
 template <int P, int W>
-static void dtw_lane_launch(int grid, const DtwArgs &a, hipStream_t s) {
+static void dtw_lane_launch(int num_cu, const DtwArgs &a, hipStream_t s) {
     const size_t lds = sizeof(float) * (size_t)(a.n + 2 * W + 1 + 4);
-    hipLaunchKernelGGL((k_dtw_lane<P, W>), dim3(grid), dim3(64), lds, s, a);
+    hipLaunchKernelGGL((k_dtw_lane<P, W>), dim3(persistent_grid(k_dtw_lane<P, W>, lds, num_cu)), dim3(64), lds, s,
+                       a);
 }
 
 using DtwLaneFn = void (*)(int, const DtwArgs &, hipStream_t);

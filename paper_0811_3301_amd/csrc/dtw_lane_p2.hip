@@ -3,10 +3,10 @@
 
 namespace lbimp {
 
-hipError_t launch_dtw_lane_p2(int w, int grid, const DtwArgs &a, hipStream_t s) {
+hipError_t launch_dtw_lane_p2(int w, int num_cu, const DtwArgs &a, hipStream_t s) {
     static const auto table = dtw_lane_table<2>(std::make_integer_sequence<int, kLaneMaxW + 1>{});
     if (w < 0 || w > kLaneMaxW) return hipErrorInvalidValue;
-    table[w](grid, a, s);
+    table[w](num_cu, a, s);
     return hipGetLastError();
 }
 

@@ -1,0 +1,160 @@
+// Banded DTW_p (Sec. 4 of Lemire, arXiv:0811.3301) with a group of lanes per pair: the band
+// is swept along anti-diagonals held in registers, neighbours exchanged by DPP lane shifts.
+// One pair costs about n dependent steps instead of n(2w+1), which is what a latency-bound
+// stage (the seeding DTWs, a few per query) needs.
+#include "device_common.h"
+
+namespace lbimp {
+
+// Cells (i, j) with |j - i| <= w.  Anti-diagonal d = i + j, band position u = j - i + w in
+// [0, 2w].  Lane l of a group holds positions u = 2l (even) and 2l + 1 (odd); step t computes
+// the even cell on diagonal de = 2t - (w & 1) and the odd cell on do = de + 1 (a position's
+// parity fixes the parity of its diagonals).  The recursion, in prefix form:
+//   even (de, 2l):   left (de-1, 2l-1) = odd of lane l-1, previous step (shift right)
+//                    up   (de-1, 2l+1) = own odd, previous step
+//                    diag (de-2, 2l)   = own even, previous step
+//   odd  (do, 2l+1): left (do-1, 2l)   = own even, this step
+//                    up   (do-1, 2l+2) = even of lane l+1, this step (shift left)
+//                    diag (do-2, 2l+1) = own odd, previous step
+// Both cells of a lane share i = (de - 2l + w) / 2; j = de - i and j + 1.  The pair's row x is
+// staged in LDS padded with +inf and the query with -inf, so any cell outside the matrix costs
+// +inf (x - y is +inf whichever side is out of range).  Lanes outside the band (2l > 2w for
+// the even cell, 2l + 1 > 2w for the odd one) are forced to +inf, which also keeps groups of
+// one wave from leaking into each other through the shifts.  The virtual cell (-1,-1) = 0 sits
+// on diagonal -2 at u = w: the even slot of lane w/2 (w even) or the odd slot of lane
+// (w-1)/2 (w odd), as the state of step -1.  The result D(n-1, n-1) is read from the same slot
+// after step n-1.  Early abandoning: a path visits one of any two consecutive anti-diagonals,
+// so min over both cells of all lanes bounds the result.
+constexpr int kWavePad = 96;  // LDS padding of x and y on each side: |i - t|, |j - t| <= 64, +9 read ahead
+
+__device__ __forceinline__ float dpp_shr1(float v) {  // lane l gets lane l-1, lane 0 gets +inf
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(kInf), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_shl1(float v) {  // lane l gets lane l+1, lane 63 gets +inf
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(kInf), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+template <int P>
+__device__ __forceinline__ float cost_add(float d, float m) {
+    return (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_dtw_wavereg(DtwArgs a, int w, int LP) {
+    extern __shared__ float sm[];
+    const int n = a.n;
+    const int span = n + 2 * kWavePad;
+    float *ys = sm;                 // [span], ys[j + pad] = y[j], -inf outside
+    float *xs = sm + span;          // [G][span], xs[g][i + pad] = x_g[i], +inf outside
+    __shared__ int cand[64];
+    const int lane = threadIdx.x;
+    const int G = 64 / LP;
+    const int g = lane / LP, l = lane % LP;
+    float *xg = xs + g * span;
+    const bool e_ok = 2 * l <= 2 * w;
+    const bool o_ok = 2 * l + 1 <= 2 * w;
+    const int slot_lane = w >> 1;   // lane (within the group) holding the start and end cells
+    const bool slot_odd = (w & 1) != 0;
+    int64_t cur_q = -1;
+    int64_t q;
+    long long b;
+    ItemCursor items(a.pl, a.prefix, a.Q, G);
+    while (items.get(q, b)) {
+        const long long jj = b * G + g;
+        const int cl = jj < pair_count(a.pl, q) ? pair_cand(a.pl, q, jj) : -1;
+        const bool active0 = cl >= 0;
+        const int c = active0 ? cl : 0;
+        __syncthreads();
+        if (l == 0) cand[g] = cl;
+        __syncthreads();
+        if (q != cur_q) {
+            const float *y = a.qd.Y + q * a.qd.ldy;
+            stage_lds(ys, span, [&](int t) {
+                const int j = t - kWavePad;
+                return (j >= 0 && j < n) ? y[j] : -kInf;
+            });
+            cur_q = q;
+        }
+        // stage every group's row (+inf padded); all groups in one pass
+        stage_lds(xs, G * span, [&](int t) {
+            const int gg = t / span;
+            const int i = t - gg * span - kWavePad;
+            const int cg = cand[gg];
+            return (cg >= 0 && i >= 0 && i < n) ? a.rows[(int64_t)cg * n + i] : kInf;
+        });
+        __syncthreads();
+        const u64 *tq = a.tkeys + q;
+        float E = kInf, O = kInf;  // state of step -1
+        if (l == slot_lane) {
+            if (slot_odd)
+                O = 0.f;
+            else
+                E = 0.f;
+        }
+        // step t reads x[i] and y[j], y[j+1] with i = t + (w - (w&1))/2 - l, j = de - i
+        const int i0 = (w - (w & 1)) / 2 - l;
+        const int j0 = -(w & 1) - i0;
+        const float *xp = xg + kWavePad + i0;
+        const float *yp = ys + kWavePad + j0;
+        bool alive = active0;
+        auto step = [&](float xi, float yj, float yj1) {
+            const float left = dpp_shr1(O);
+            float Ee = cost_add<P>(xi - yj, __builtin_fminf(__builtin_fminf(left, O), E));
+            Ee = e_ok ? Ee : kInf;
+            const float up = dpp_shl1(Ee);
+            float Oo = cost_add<P>(xi - yj1, __builtin_fminf(__builtin_fminf(Ee, up), O));
+            O = o_ok ? Oo : kInf;
+            E = Ee;
+        };
+        // blocks of 8 steps: the 8 x and 9 y values of a block are read from LDS up front
+        int t0 = 0;
+        for (; t0 + 8 <= n; t0 += 8) {
+            float xv[8], yv[9];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xv[u] = xp[t0 + u];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) yv[u] = yp[t0 + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) step(xv[u], yv[u], yv[u + 1]);
+            if (a.abandon) {
+                float m = fminf(E, O);
+                for (int off = LP >> 1; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
+                const u64 th = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (alive && make_key(m, c) >= th) alive = false;
+                if (!__any(alive)) break;
+            }
+        }
+        if (t0 + 8 > n)
+            for (int t = t0; t < n; ++t) step(xp[t], yp[t], yp[t + 1]);
+        const float dfin = slot_odd ? O : E;
+        const bool owner = l == slot_lane;
+        publish<P>(owner && alive, dfin, c, q, a.best, a.thr, a.res, a.ldres, a.rescnt, a.out_root);
+        if (a.abandoned && owner && active0 && !alive) atomicAdd(&a.abandoned[q], 1);
+    }
+}
+
+// Lanes per pair: the smallest power of two above w, widened until the staged rows fit in LDS.
+static int wave_lanes(int n, int w) {
+    int lp = 1;
+    while (lp < w + 1) lp <<= 1;
+    while (lp < 64 && sizeof(float) * (size_t)(n + 2 * kWavePad) * (1 + 64 / lp) > kLdsBudget) lp <<= 1;
+    return lp;
+}
+
+int dtw_wave_batch(int n, int w) { return 64 / wave_lanes(n, w); }
+
+hipError_t launch_dtw_wavereg(int p, int w, int num_cu, const DtwArgs &a, hipStream_t s) {
+    if (w > kLaneMaxW) return hipErrorInvalidValue;
+    const int LP = wave_lanes(a.n, w);
+    const size_t lds = sizeof(float) * (size_t)(a.n + 2 * kWavePad) * (1 + 64 / LP);
+    if (lds > kLdsBudget) return hipErrorInvalidValue;
+    if (p == 1)
+        hipLaunchKernelGGL(k_dtw_wavereg<1>, dim3(persistent_grid(k_dtw_wavereg<1>, lds, num_cu)), dim3(64), lds, s,
+                           a, w, LP);
+    else
+        hipLaunchKernelGGL(k_dtw_wavereg<2>, dim3(persistent_grid(k_dtw_wavereg<2>, lds, num_cu)), dim3(64), lds, s,
+                           a, w, LP);
+    return hipGetLastError();
+}
+
+}  // namespace lbimp

@@ -14,6 +14,7 @@ constexpr float kInf = __builtin_huge_valf();
 constexpr unsigned long long kNoKey = ~0ull;  // larger than every (distance, index) key
 constexpr size_t kLdsBudget = 65536;          // dynamic LDS per workgroup used by any kernel
 constexpr int kLaneMaxW = 63;                 // widest band (half-width) of the lane-per-pair DTW
+constexpr int kLbiRegMaxW = 52;               // widest band of the register-state LB_Improved
 
 // Launch wrappers.  Every pointer is device memory; all launches go to `s`.
 // Each returns hipSuccess or the launch error.
@@ -34,12 +35,18 @@ hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w
 // LB_Keogh^p of every interleaved candidate against Q padded envelopes (stride ld4 float4).
 // Writes out[q*ldo + c] for c < N (and +inf for c in [N, ldo) when pad_inf).  root: take the
 // p-th root (public output) instead of leaving the pow-domain value.
+// wmin (optional, nn search only): wmin[q][v] = smallest (S1, index) key over the candidates of
+// sweep wave v, v < sweep_waves(N, Q).
 hipError_t launch_lbk_sweep(int p, const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le,
-                            int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root, hipStream_t s);
+                            int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root,
+                            unsigned long long *wmin, hipStream_t s);
+int64_t sweep_waves(int64_t N, int64_t Q);
 
-// Per query: pick S candidates of smallest first-pass sum (approximately the S smallest)
-// into seeds[q][0..S) and set their S1 entries to +inf.  S <= 64, S <= N.
-hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int S, int *seeds, hipStream_t s);
+// Per query: pick S candidates of small first-pass sum into seeds[q][0..S) and set their S1
+// entries to +inf.  From the whole S1 row (wmin == nullptr), or from the nw per-wave minima of
+// the sweep (one candidate per sweep wave).  S <= 64, S <= number of sources.
+hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int S, const unsigned long long *wmin,
+                               int64_t nw, int *seeds, hipStream_t s);
 
 // list[q][*] <- candidates c < N with key(S1[q][c], c) < thr[q]; cnt[q] += number kept.
 hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, const unsigned long long *thr,
@@ -72,19 +79,21 @@ struct QueryData {
 // (single query).  prefix: items of `lbi_batch(n, w)` pairs; 0 means the per-lane envelope
 // state of this (n, w) does not fit in LDS.
 int lbi_batch(int n, int w);
-hipError_t launch_lbi(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const float *S1,
-                      int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int grid,
+hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, QueryData qd, PairList pl, const float *S1,
+                      int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
-                      hipStream_t s);
+                      bool pipeline, hipStream_t s);
 
 // Banded DTW over a pair list.  best (k = 1): per-query best key, updated by atomicMin and used
 // for early abandoning.  thr/res/rescnt (k > 1): keys below thr[q] are appended to res[q].
 // out_root (single query): out_root[c] = DTW_p.  abandon=false computes every DTW in full.
-int dtw_batch(int n, int w);
+// low_latency: a group of lanes per pair (few pairs, each finished quickly) instead of a lane
+// per pair (many pairs, highest throughput).  Items hold dtw_batch(n, w, low_latency) pairs.
+int dtw_batch(int n, int w, bool low_latency);
 hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const long long *prefix,
-                      int64_t Q, int *ctr, int grid, unsigned long long *best, const unsigned long long *thr,
+                      int64_t Q, int *ctr, int num_cu, unsigned long long *best, const unsigned long long *thr,
                       unsigned long long *res, int64_t ldres, int *rescnt, int *abandoned, float *out_root,
-                      bool abandon, hipStream_t s);
+                      bool abandon, bool low_latency, hipStream_t s);
 
 // k-th smallest key of res[q][0..min(rescnt[q], 64)) into thr[q] (kNoKey if fewer than k).
 hipError_t launch_kth_key(const unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k,

@@ -15,6 +15,7 @@ namespace lbimp {
 // block B-1 at offset o+1 (or at B's start when o = K-1), whose suffix max/min h was stored
 // by a backward walk over block B-1.  Only h (2(K+1) floats per lane) lives in LDS.
 int lbi_batch(int n, int w) {
+    if (w <= kLbiRegMaxW) return 64;
     const size_t K = 2 * (size_t)w + 1;
     const size_t fixed = 3 * 4 * (size_t)n;
     if (fixed >= kLdsBudget) return 0;
@@ -49,14 +50,13 @@ __global__ __launch_bounds__(64) void k_lbi(const float *__restrict__ rows, int 
     int64_t cur_q = -1;
     int64_t q;
     long long b;
-    while (next_item(ctr, prefix, Q, q, b)) {
+    ItemCursor items(pl, prefix, Q, WL);
+    while (items.get(q, b)) {
         if (q != cur_q) {
             __syncthreads();
-            for (int i = lane; i < n; i += 64) {
-                sU[i] = qd.U[q * qd.ldq + i];
-                sL[i] = qd.L[q * qd.ldq + i];
-                sY[i] = qd.Y[q * qd.ldy + i];
-            }
+            stage_lds(sU, n, [&](int i) { return qd.U[q * qd.ldq + i]; });
+            stage_lds(sL, n, [&](int i) { return qd.L[q * qd.ldq + i]; });
+            stage_lds(sY, n, [&](int i) { return qd.Y[q * qd.ldy + i]; });
             __syncthreads();
             cur_q = q;
         }
@@ -122,18 +122,22 @@ __global__ __launch_bounds__(64) void k_lbi(const float *__restrict__ rows, int 
     }
 }
 
-hipError_t launch_lbi(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const float *S1,
-                      int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int grid,
+hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, QueryData qd, PairList pl, const float *S1,
+                      int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
-                      hipStream_t s) {
+                      bool pipeline, hipStream_t s) {
+    if (w <= kLbiRegMaxW) {
+        LbiArgs a{rows, db_bytes, n, qd, pl, S1, ldS, prefix, Q, ctr, thr, list2, ldl2, cnt2, out_root, pipeline};
+        return p == 1 ? launch_lbi_reg_p1(w, num_cu, a, s) : launch_lbi_reg_p2(w, num_cu, a, s);
+    }
     const int WL = lbi_batch(n, w);
     const int K = 2 * w + 1;
     size_t lds = sizeof(float) * (3 * (size_t)n + 2 * (size_t)(K + 1) * WL);
     if (p == 1)
-        hipLaunchKernelGGL(k_lbi<1>, dim3(grid), dim3(64), lds, s, rows, n, w, qd, pl, S1, ldS, prefix, Q, ctr, WL,
+        hipLaunchKernelGGL(k_lbi<1>, dim3(persistent_grid(k_lbi<1>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, S1, ldS, prefix, Q, ctr, WL,
                            thr, list2, ldl2, cnt2, out_root);
     else
-        hipLaunchKernelGGL(k_lbi<2>, dim3(grid), dim3(64), lds, s, rows, n, w, qd, pl, S1, ldS, prefix, Q, ctr, WL,
+        hipLaunchKernelGGL(k_lbi<2>, dim3(persistent_grid(k_lbi<2>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, S1, ldS, prefix, Q, ctr, WL,
                            thr, list2, ldl2, cnt2, out_root);
     return hipGetLastError();
 }
@@ -154,7 +158,8 @@ __global__ __launch_bounds__(64) void k_dtw_wave(const float *__restrict__ rows,
     const int lane = threadIdx.x;
     int64_t q;
     long long b;
-    while (next_item(ctr, prefix, Q, q, b)) {
+    ItemCursor items(pl, prefix, Q, 1);
+    while (items.get(q, b)) {
         const bool valid = b < pair_count(pl, q);
         if (!valid) continue;
         const int c = pair_cand(pl, q, b);
@@ -211,22 +216,28 @@ __global__ __launch_bounds__(64) void k_dtw_wave(const float *__restrict__ rows,
     }
 }
 
-int dtw_batch(int n, int w) { return w <= kLaneMaxW ? 64 : 1; }
+int dtw_batch(int n, int w, bool low_latency) {
+    if (w > kLaneMaxW) return 1;
+    return low_latency ? dtw_wave_batch(n, w) : 64;
+}
 
 hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const long long *prefix,
-                      int64_t Q, int *ctr, int grid, unsigned long long *best, const unsigned long long *thr,
+                      int64_t Q, int *ctr, int num_cu, unsigned long long *best, const unsigned long long *thr,
                       unsigned long long *res, int64_t ldres, int *rescnt, int *abandoned, float *out_root,
-                      bool abandon, hipStream_t s) {
+                      bool abandon, bool low_latency, hipStream_t s) {
     if (w <= kLaneMaxW) {
-        DtwArgs a{rows, n, qd, pl, prefix, Q, ctr, best, thr, res, ldres, rescnt, abandoned, out_root, abandon};
-        return p == 1 ? launch_dtw_lane_p1(w, grid, a, s) : launch_dtw_lane_p2(w, grid, a, s);
+        const u64 *tkeys = best ? best : thr;
+        if (!tkeys) return hipErrorInvalidValue;  // callers pass a threshold array, kNoKey-filled if unused
+        DtwArgs a{rows, n, qd, pl, prefix, Q, ctr, best, thr, res, ldres, rescnt, abandoned, out_root, abandon, tkeys};
+        if (low_latency) return launch_dtw_wavereg(p, w, num_cu, a, s);
+        return p == 1 ? launch_dtw_lane_p1(w, num_cu, a, s) : launch_dtw_lane_p2(w, num_cu, a, s);
     }
     const size_t lds = sizeof(float) * (3 * (size_t)n + 3);
     if (p == 1)
-        hipLaunchKernelGGL(k_dtw_wave<1>, dim3(grid), dim3(64), lds, s, rows, n, w, qd, pl, prefix, Q, ctr, best, thr,
+        hipLaunchKernelGGL(k_dtw_wave<1>, dim3(persistent_grid(k_dtw_wave<1>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, prefix, Q, ctr, best, thr,
                            res, ldres, rescnt, abandoned, out_root, abandon);
     else
-        hipLaunchKernelGGL(k_dtw_wave<2>, dim3(grid), dim3(64), lds, s, rows, n, w, qd, pl, prefix, Q, ctr, best, thr,
+        hipLaunchKernelGGL(k_dtw_wave<2>, dim3(persistent_grid(k_dtw_wave<2>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, prefix, Q, ctr, best, thr,
                            res, ldres, rescnt, abandoned, out_root, abandon);
     return hipGetLastError();
 }

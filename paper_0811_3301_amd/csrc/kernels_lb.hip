@@ -159,7 +159,7 @@ template <int P, int QG, int CPL, bool ROOT>
 __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il, int64_t T, int64_t N, int n4,
                                                     const float4 *__restrict__ Ue, const float4 *__restrict__ Le,
                                                     int ld4, int64_t Q, float *__restrict__ out, int64_t ldo,
-                                                    bool pad_inf) {
+                                                    bool pad_inf, unsigned long long *__restrict__ wmin, int64_t ldw) {
     constexpr int ICH = 32;
     __shared__ float4 sU[QG][ICH];
     __shared__ float4 sL[QG][ICH];
@@ -210,6 +210,30 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
             }
         }
     }
+    if (wmin) {
+        // smallest (value, index) key of this wave's candidates, per query: seed candidates
+        const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
+#pragma unroll
+        for (int a = 0; a < QG; ++a) {
+            unsigned long long k = kNoKey;
+#pragma unroll
+            for (int b = 0; b < CPL; ++b) {
+                const int64_t c = (tile0 + b) * 64 + lane;
+                if (tv[b] && c < N) {
+                    unsigned long long kb = ((unsigned long long)__float_as_uint(acc[a][b]) << 32) | (unsigned long long)c;
+                    k = kb < k ? kb : k;
+                }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                unsigned hi = __shfl_xor((unsigned)(k >> 32), off);
+                unsigned lo = __shfl_xor((unsigned)k, off);
+                unsigned long long o = ((unsigned long long)hi << 32) | lo;
+                k = o < k ? o : k;
+            }
+            if (lane == 0 && q0 + a < Q) wmin[(q0 + a) * ldw + wid] = k;
+        }
+    }
 #pragma unroll
     for (int a = 0; a < QG; ++a) {
         const int64_t q = q0 + a;
@@ -228,30 +252,38 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
 
 template <int P, int QG, int CPL, bool ROOT>
 static hipError_t sweep_variant(const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le, int ld4,
-                                int64_t Q, float *out, int64_t ldo, bool pad_inf, hipStream_t s) {
+                                int64_t Q, float *out, int64_t ldo, bool pad_inf, unsigned long long *wmin,
+                                hipStream_t s) {
     int64_t T = (N + 63) / 64;
     dim3 grid((unsigned)((T + 4 * CPL - 1) / (4 * CPL)), (unsigned)((Q + QG - 1) / QG));
     hipLaunchKernelGGL((k_lbk_sweep<P, QG, CPL, ROOT>), grid, dim3(256), 0, s, il, T, N, n4, Ue, Le, ld4, Q, out,
-                       ldo, pad_inf);
+                       ldo, pad_inf, wmin, (int64_t)grid.x * 4);
     return hipGetLastError();
 }
 
+int64_t sweep_waves(int64_t N, int64_t Q) {
+    const int64_t T = (N + 63) / 64;
+    const int cpl = Q == 1 ? 1 : 2;
+    return (T + 4 * cpl - 1) / (4 * cpl) * 4;
+}
+
 hipError_t launch_lbk_sweep(int p, const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le,
-                            int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root, hipStream_t s) {
+                            int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root,
+                            unsigned long long *wmin, hipStream_t s) {
     if (N == 0 || Q == 0) return hipSuccess;
     // Query-group size: envelopes of QG queries are padded to a multiple of QG by the caller.
     if (Q == 1) {
         if (p == 1)
-            return root ? sweep_variant<1, 1, 1, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s)
-                        : sweep_variant<1, 1, 1, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s);
-        return root ? sweep_variant<2, 1, 1, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s)
-                    : sweep_variant<2, 1, 1, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s);
+            return root ? sweep_variant<1, 1, 1, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
+                        : sweep_variant<1, 1, 1, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+        return root ? sweep_variant<2, 1, 1, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
+                    : sweep_variant<2, 1, 1, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
     }
     if (p == 1)
-        return root ? sweep_variant<1, 16, 2, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s)
-                    : sweep_variant<1, 16, 2, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s);
-    return root ? sweep_variant<2, 16, 2, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s)
-                : sweep_variant<2, 16, 2, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, s);
+        return root ? sweep_variant<1, 16, 2, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
+                    : sweep_variant<1, 16, 2, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+    return root ? sweep_variant<2, 16, 2, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
+                : sweep_variant<2, 16, 2, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
 }
 
 // ------------------------------------------------------------------ seed selection
@@ -260,14 +292,18 @@ hipError_t launch_lbk_sweep(int p, const float4 *il, int64_t N, int n4, const fl
 // Each thread keeps its 4 smallest (value, index) keys; the 1024 keys of the block are sorted
 // bitonically in LDS and the first S taken.  Approximate top-S is enough: any threshold that
 // is the DTW of some candidate is a valid (never too small) best-so-far.
-__global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, int64_t ldS, int64_t N, int S,
-                                                       int *__restrict__ seeds) {
+template <bool FROM_KEYS>
+__global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, int64_t ldS, int64_t N,
+                                                       const unsigned long long *__restrict__ wmin, int64_t nw,
+                                                       int S, int *__restrict__ seeds) {
     __shared__ unsigned long long keys[1024];
     const int64_t q = blockIdx.x;
     float *row = S1 + q * ldS;
     unsigned long long top[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
-    for (int64_t c = threadIdx.x; c < N; c += 256) {
-        unsigned long long k = ((unsigned long long)__float_as_uint(row[c]) << 32) | (unsigned long long)c;
+    const int64_t count = FROM_KEYS ? nw : N;
+    for (int64_t c = threadIdx.x; c < count; c += 256) {
+        unsigned long long k = FROM_KEYS ? wmin[q * nw + c]
+                                         : ((unsigned long long)__float_as_uint(row[c]) << 32) | (unsigned long long)c;
         if (k < top[3]) {
             top[3] = k;
 #pragma unroll
@@ -306,9 +342,13 @@ __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, in
     }
 }
 
-hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int S, int *seeds, hipStream_t s) {
+hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int S, const unsigned long long *wmin,
+                               int64_t nw, int *seeds, hipStream_t s) {
     if (Q == 0 || S == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_select_seeds, dim3((unsigned)Q), dim3(256), 0, s, S1, ldS, N, S, seeds);
+    if (wmin)
+        hipLaunchKernelGGL(k_select_seeds<true>, dim3((unsigned)Q), dim3(256), 0, s, S1, ldS, N, wmin, nw, S, seeds);
+    else
+        hipLaunchKernelGGL(k_select_seeds<false>, dim3((unsigned)Q), dim3(256), 0, s, S1, ldS, N, wmin, nw, S, seeds);
     return hipGetLastError();
 }
 
@@ -319,7 +359,9 @@ hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int
 __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, int64_t ldS, int64_t N,
                                                   const unsigned long long *__restrict__ thr, int *__restrict__ list,
                                                   int64_t ldl, int *__restrict__ cnt) {
-    constexpr int CH = 8;
+    constexpr int CH = 16;
+    __shared__ int wtot[4];
+    __shared__ int wbase[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t q = blockIdx.y;
     const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64 * CH;
@@ -338,10 +380,19 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, i
         masks[ch] = __ballot(keep);
         total += __popcll(masks[ch]);
     }
+    if (lane == 0) wtot[wave] = total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int sum = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+        int pos = sum ? atomicAdd(&cnt[q], sum) : 0;
+        for (int v = 0; v < 4; ++v) {
+            wbase[v] = pos;
+            pos += wtot[v];
+        }
+    }
+    __syncthreads();
     if (total == 0) return;
-    int pos = 0;
-    if (lane == 0) pos = atomicAdd(&cnt[q], total);
-    pos = __shfl(pos, 0);
+    int pos = wbase[wave];
     const unsigned long long below = (1ull << lane) - 1ull;
     int *out = list + q * ldl;
 #pragma unroll
@@ -354,7 +405,7 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, i
 hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, const unsigned long long *thr,
                           int *list, int64_t ldl, int *cnt, hipStream_t s) {
     if (N == 0 || Q == 0) return hipSuccess;
-    int64_t per_block = 4 * 64 * 8;
+    int64_t per_block = 4 * 64 * 16;
     dim3 grid((unsigned)((N + per_block - 1) / per_block), (unsigned)Q);
     hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, S1, ldS, N, thr, list, ldl, cnt);
     return hipGetLastError();

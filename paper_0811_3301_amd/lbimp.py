@@ -40,6 +40,7 @@ SIGNATURES = {
     "lbimp_ctx_set_stream": (ctypes.c_int, [_vp, _vp]),
     "lbimp_ctx_destroy": (None, [_vp]),
     "lbimp_ctx_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lbimp_ctx_set_option": (ctypes.c_int, [_vp, ctypes.c_char_p, _i64]),
     "lbimp_ctx_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int]),
     "lbimp_db_create": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(_vp)]),
     "lbimp_db_destroy": (None, [_vp]),
@@ -160,6 +161,10 @@ def lbimp_db_create(ctx: Ctx, rows: torch.Tensor) -> Db:
 
 def lbimp_ctx_set_timing(ctx: Ctx, enable: bool):
     _check(_lib.lbimp_ctx_set_timing(ctx.h, int(bool(enable))), "lbimp_ctx_set_timing")
+
+
+def lbimp_ctx_set_option(ctx: Ctx, name: str, value: int):
+    _check(_lib.lbimp_ctx_set_option(ctx.h, name.encode(), int(value)), "lbimp_ctx_set_option")
 
 
 def lbimp_ctx_stage_times(ctx: Ctx) -> dict:

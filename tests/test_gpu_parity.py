@@ -127,13 +127,18 @@ def test_lb_improved(L, ctx, N, n, w, p):
 # ------------------------------------------------------------------ DTW
 @pytest.mark.parametrize("N,n,w", [(70, 1, 0), (70, 2, 1), (130, 64, 0), (130, 128, 13), (65, 256, 26),
                                    (33, 512, 51), (20, 300, 63), (10, 200, 64), (8, 512, 102), (4, 97, 500),
-                                   (3, 1024, 205)])
+                                   (3, 1024, 205), (67, 77, 2), (45, 33, 7), (66, 4096, 31), (5, 40, 40)])
 @pytest.mark.parametrize("p", [1, 2])
-def test_dtw_band(L, ctx, N, n, w, p):
-    _say(f"dtw_band N={N} n={n} w={w} p={p}")
+@pytest.mark.parametrize("group", [0, 1])
+def test_dtw_band(L, ctx, N, n, w, p, group):
+    _say(f"dtw_band N={N} n={n} w={w} p={p} group_per_pair={group}")
     X = walks(N, n, 7)
     y = walks(1, n, 8)[0]
-    d = L.lbimp_dtw_band(ctx, to_dev(X), to_dev(y), w, p).cpu().numpy()
+    L.lbimp_ctx_set_option(ctx, "dtw_group_per_pair", group)
+    try:
+        d = L.lbimp_dtw_band(ctx, to_dev(X), to_dev(y), w, p).cpu().numpy()
+    finally:
+        L.lbimp_ctx_set_option(ctx, "dtw_group_per_pair", 0)
     D = native.dtw_pow_many(X, y, R.effective_band(n, w), p)
     assert_close(d, D ** (1.0 / p), lp_scale(X, y, p), "dtw_band")
 
