@@ -23,9 +23,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "1-NN DTW queries/sec (LB_Improved vs LB_Keogh vs brute); LB GB/s; p50/p99"
-VALU_PEAK_OPS = 256 * 64 * 2.4e9      # fp32 VALU lane-instructions per second (unpacked)
+# fp32 vector peak 157.3 TFLOP/s counts an FMA as 2 flops: 78.6e12 VALU lane-slots per second
+# (256 CUs x 128 lane-ops per clock x 2.4 GHz).  One LB_Keogh element is 2 comparisons (one
+# 3-operand med3, which issues in two slots), a subtract and an accumulate: 4 slots.  A DTW cell
+# is a subtract, a 3-way min (two slots) and an accumulate: 4 slots.
+VALU_PEAK_OPS = 157.3e12 / 2
 HBM_PEAK_GBPS = 8000.0
-LBK_OPS_PER_ELEM = 3                  # clamp (both comparisons, one med3), subtract, accumulate
+LBK_OPS_PER_ELEM = 4
+DTW_OPS_PER_CELL = 4
+
+
+def sweep_traffic():
+    """HBM bytes per sweep launch from the committed PMC summary, if it was taken on the
+    current sweep kernel source (else None)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_0811_3301_amd", "csrc", "kernels_lb.hip")
+    prof = os.path.join(ROOT, "profiles", "lbk_sweep_rw256_traffic.md")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    fields = {}
+    for line in open(prof):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256_16") != sha:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -124,6 +151,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quick", action="store_true", help="two-pass mode only (for profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
@@ -132,6 +161,15 @@ def main():
 
     import torch
     from paper_0811_3301_amd import gen, lbimp as L
+
+    if args.copy_probe:
+        a = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4}), flush=True)
+        return
 
     L.load()
     N, n, Q, w = 100_000, 256, 256, 26
@@ -172,7 +210,13 @@ def main():
     achieved = LBK_OPS_PER_ELEM * elems / (sweep_ms / 1e3) / 1e12
     roofline = dict(bound="alu", kernel="k_lbk_sweep (LB_Keogh of every query x candidate)",
                     achieved=achieved, peak=VALU_PEAK_OPS / 1e12, unit="TOP/s", frac=achieved * 1e12 / VALU_PEAK_OPS,
-                    traffic=None, kernel_ms=sweep_ms, ops_per_element=LBK_OPS_PER_ELEM, elements=elems)
+                    traffic=sweep_traffic(), kernel_ms=sweep_ms, ops_per_element=LBK_OPS_PER_ELEM, elements=elems,
+                    algorithmic_hbm_bytes=N * n * 4 * (Q // 16) + Q * ((N + 63) // 64 * 64) * 4)
+    if "brute" in modes:
+        cells = Q * N * (n * (2 * w + 1) - w * (w + 1))
+        t = modes["brute"]["ms_per_step"] / 1e3
+        modes["brute"]["dtw_cells_per_s"] = cells / t
+        modes["brute"]["dtw_frac_of_alu_peak"] = DTW_OPS_PER_CELL * cells / t / VALU_PEAK_OPS
 
     lbg = None
     if not args.quick:

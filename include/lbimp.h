@@ -83,7 +83,10 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *   "lbi_pipeline"  0/1 (default 1): software-pipelined loads in the LB_Improved pass;
  *   "dtw_group_per_pair"  0/1 (default 0): lbimp_dtw_band computes each DTW with a group of
  *                   lanes along anti-diagonals (the kernel of the seeding stage) instead of
- *                   one lane per pair; bands with w > 63 always use the anti-diagonal kernel.
+ *                   one lane per pair; bands with w > 63 always use the anti-diagonal kernel;
+ *   "sweep_shape"   0..5 (default 0): tiling of the multi-query LB_Keogh sweep (queries per
+ *                   block x candidate tiles per wave: 0 = 16x2, 2 = 8x4, 3 = 32x2, 4 = 16x4,
+ *                   5 = 8x2, 1 = 16x2).
  * Returns LBIMP_E_INVALID for an unknown name or an out-of-range value. */
 int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
 

@@ -40,7 +40,6 @@ static int fail(int code, const char *fmt, ...) {
 namespace {
 
 constexpr int kStages = 8;
-constexpr int kQueryGroup = 16;  // the multi-query sweep processes queries in groups of 16
 constexpr int kMaxSeeds = 64;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -71,6 +70,7 @@ struct lbimp_ctx {
     int seeds = 32;             // option "seeds"
     bool lbi_pipeline = true;   // option "lbi_pipeline"
     bool dtw_low_latency = false;  // option "dtw_group_per_pair" (lbimp_dtw_band only)
+    int sweep_shape = 0;           // option "sweep_shape"
     hipEvent_t ev[kStages + 1] = {};
 };
 
@@ -177,6 +177,9 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         ctx->lbi_pipeline = value != 0;
     } else if (!strcmp(name, "dtw_group_per_pair")) {
         ctx->dtw_low_latency = value != 0;
+    } else if (!strcmp(name, "sweep_shape")) {
+        if (value < 0 || value > 5) return fail(LBIMP_E_INVALID, "sweep_shape must be in [0, 5]");
+        ctx->sweep_shape = (int)value;
     } else {
         return fail(LBIMP_E_INVALID, "unknown option '%s'", name);
     }
@@ -270,7 +273,7 @@ int lbimp_lb_keogh(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, const f
     float *Ld = c2.take<float>((size_t)n4 * 4);
     HIPTRY(launch_pack(x, N, n, il, ctx->stream));
     HIPTRY(launch_pad_env(U, L, 1, 1, n, Ud, Ld, n4 * 4, ctx->stream));
-    HIPTRY(launch_lbk_sweep(p, il, N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4, 1, lb,
+    HIPTRY(launch_lbk_sweep(p, 0, il, N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4, 1, lb,
                             N, false, true, nullptr, ctx->stream));
     return LBIMP_OK;
 }
@@ -283,7 +286,8 @@ int lbimp_db_lb_keogh(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const 
     if (Q == 0 || db->N == 0) return LBIMP_OK;
     if (!U || !L || !lb) return fail(LBIMP_E_INVALID, "null pointer");
     const int n = db->n, n4 = (n + 3) / 4;
-    const int64_t Qp = Q == 1 ? 1 : (Q + kQueryGroup - 1) / kQueryGroup * kQueryGroup;
+    const int qg = sweep_query_group(ctx->sweep_shape, Q);
+    const int64_t Qp = (Q + qg - 1) / qg * qg;
     Carver cv{nullptr};
     cv.take<float>((size_t)Qp * n4 * 4);
     cv.take<float>((size_t)Qp * n4 * 4);
@@ -292,7 +296,7 @@ int lbimp_db_lb_keogh(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const 
     float *Ud = c2.take<float>((size_t)Qp * n4 * 4);
     float *Ld = c2.take<float>((size_t)Qp * n4 * 4);
     HIPTRY(launch_pad_env(U, L, Q, Qp, n, Ud, Ld, n4 * 4, ctx->stream));
-    HIPTRY(launch_lbk_sweep(p, db->il, db->N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4,
+    HIPTRY(launch_lbk_sweep(p, ctx->sweep_shape, db->il, db->N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4,
                             Q, lb, db->N, false, true, nullptr, ctx->stream));
     return LBIMP_OK;
 }
@@ -326,7 +330,7 @@ int lbimp_lb_improved(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, cons
     hipStream_t s = ctx->stream;
     HIPTRY(launch_pack(x, N, n, il, s));
     HIPTRY(launch_pad_env(U, L, 1, 1, n, Ud, Ld, n4 * 4, s));
-    HIPTRY(launch_lbk_sweep(p, il, N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4, 1, S1,
+    HIPTRY(launch_lbk_sweep(p, 0, il, N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4, 1, S1,
                             N, false, false, nullptr, s));
     HIPTRY(launch_fill_i32(ctr, 0, 1, s));
     HIPTRY(launch_items_prefix(nullptr, N, 1, WL, prefix, s));
@@ -381,7 +385,8 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     const int64_t N = db->N;
     const int wb = band_of(n, w);
     const int64_t Np = (N + 63) / 64 * 64;
-    const int64_t Qp = (Q + kQueryGroup - 1) / kQueryGroup * kQueryGroup;
+    const int qg = sweep_query_group(ctx->sweep_shape, Q);
+    const int64_t Qp = (Q + qg - 1) / qg * qg;
     const bool brute = mode == LBIMP_MODE_BRUTE;
     const bool improved = mode == LBIMP_MODE_IMPROVED;
     const int S = brute ? 0 : (int)std::min<int64_t>(std::max(ctx->seeds, k), N);
@@ -410,7 +415,7 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
 
     // ---- workspace layout
     // Seeds come from the per-wave minima of the sweep once there are enough of them.
-    const int64_t nw = sweep_waves(N, Q);
+    const int64_t nw = sweep_waves(ctx->sweep_shape, N, Q);
     const bool seeds_from_minima = !brute && nw >= 4 * (int64_t)kMaxSeeds;
     auto layout = [&](Carver &c, float *&Ue, float *&Le, float *&S1, int *&seeds, u64 *&best, u64 *&thr, u64 *&res,
                       int *&list1, int *&list2, int *&counters, long long *&prefix, u64 *&wmin) {
@@ -461,7 +466,7 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
                           k == 1 ? nullptr : thr, res, ldres, rescnt, nullptr, nullptr, false, false, s));
     } else {
         // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
-        HIPTRY(launch_lbk_sweep(p, db->il, N, n4, reinterpret_cast<float4 *>(Ue), reinterpret_cast<float4 *>(Le),
+        HIPTRY(launch_lbk_sweep(p, ctx->sweep_shape, db->il, N, n4, reinterpret_cast<float4 *>(Ue), reinterpret_cast<float4 *>(Le),
                                 n4, Q, S1, Np, true, false, wmin, s));
         stage_mark(ctx, 2);
         HIPTRY(launch_select_seeds(S1, Np, N, Q, S, wmin, nw, seeds, s));

@@ -37,10 +37,13 @@ hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w
 // p-th root (public output) instead of leaving the pow-domain value.
 // wmin (optional, nn search only): wmin[q][v] = smallest (S1, index) key over the candidates of
 // sweep wave v, v < sweep_waves(N, Q).
-hipError_t launch_lbk_sweep(int p, const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le,
-                            int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root,
+// shape: tiling variant (0 = default); rows of Ue/Le must be padded to a multiple of
+// sweep_query_group(shape, Q) queries.
+hipError_t launch_lbk_sweep(int p, int shape, const float4 *il, int64_t N, int n4, const float4 *Ue,
+                            const float4 *Le, int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root,
                             unsigned long long *wmin, hipStream_t s);
-int64_t sweep_waves(int64_t N, int64_t Q);
+int sweep_query_group(int shape, int64_t Q);
+int64_t sweep_waves(int shape, int64_t N, int64_t Q);
 
 // Per query: pick S candidates of small first-pass sum into seeds[q][0..S) and set their S1
 // entries to +inf.  From the whole S1 row (wmin == nullptr), or from the nw per-wave minima of

@@ -261,29 +261,66 @@ static hipError_t sweep_variant(const float4 *il, int64_t N, int n4, const float
     return hipGetLastError();
 }
 
-int64_t sweep_waves(int64_t N, int64_t Q) {
+// Sweep shapes: queries per block (QG) x candidate tiles per wave (CPL).  Shape 0 serves a
+// single query (the HBM-bound form); the others trade LDS broadcast traffic (less with more
+// tiles per wave) against waves in flight.
+static void shape_of(int shape, int64_t Q, int &qg, int &cpl) {
+    if (Q == 1) {
+        qg = 1;
+        cpl = 4;
+        return;
+    }
+    switch (shape) {
+        case 2: qg = 8; cpl = 4; break;
+        case 3: qg = 32; cpl = 2; break;
+        case 4: qg = 16; cpl = 4; break;
+        case 5: qg = 8; cpl = 2; break;
+        default: qg = 16; cpl = 2; break;
+    }
+}
+
+int sweep_query_group(int shape, int64_t Q) {
+    int qg, cpl;
+    shape_of(shape, Q, qg, cpl);
+    return qg;
+}
+
+int64_t sweep_waves(int shape, int64_t N, int64_t Q) {
+    int qg, cpl;
+    shape_of(shape, Q, qg, cpl);
     const int64_t T = (N + 63) / 64;
-    const int cpl = Q == 1 ? 1 : 2;
     return (T + 4 * cpl - 1) / (4 * cpl) * 4;
 }
 
-hipError_t launch_lbk_sweep(int p, const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le,
-                            int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root,
+template <int P, bool ROOT>
+static hipError_t sweep_p(int qg, int cpl, const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le,
+                          int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, unsigned long long *wmin,
+                          hipStream_t s) {
+#define LBIMP_SWEEP(QG, CPL) \
+    if (qg == QG && cpl == CPL) \
+        return sweep_variant<P, QG, CPL, ROOT>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+    LBIMP_SWEEP(1, 4)
+    LBIMP_SWEEP(16, 2)
+    LBIMP_SWEEP(8, 4)
+    LBIMP_SWEEP(32, 2)
+    LBIMP_SWEEP(16, 4)
+    LBIMP_SWEEP(8, 2)
+#undef LBIMP_SWEEP
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_lbk_sweep(int p, int shape, const float4 *il, int64_t N, int n4, const float4 *Ue,
+                            const float4 *Le, int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root,
                             unsigned long long *wmin, hipStream_t s) {
     if (N == 0 || Q == 0) return hipSuccess;
-    // Query-group size: envelopes of QG queries are padded to a multiple of QG by the caller.
-    if (Q == 1) {
-        if (p == 1)
-            return root ? sweep_variant<1, 1, 1, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
-                        : sweep_variant<1, 1, 1, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
-        return root ? sweep_variant<2, 1, 1, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
-                    : sweep_variant<2, 1, 1, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
-    }
+    int qg, cpl;
+    shape_of(shape, Q, qg, cpl);
+    // query envelopes are padded by the caller to a multiple of sweep_query_group(shape, Q)
     if (p == 1)
-        return root ? sweep_variant<1, 16, 2, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
-                    : sweep_variant<1, 16, 2, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
-    return root ? sweep_variant<2, 16, 2, true>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
-                : sweep_variant<2, 16, 2, false>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+        return root ? sweep_p<1, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
+                    : sweep_p<1, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+    return root ? sweep_p<2, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
+                : sweep_p<2, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
 }
 
 // ------------------------------------------------------------------ seed selection

@@ -91,18 +91,23 @@ def test_lb_keogh(L, ctx, N, n, p):
     assert_close(lb, s1 ** (1.0 / p), lp_scale(X, y, p), "lb_keogh")
 
 
-@pytest.mark.parametrize("Q", [1, 3, 17])
+@pytest.mark.parametrize("Q", [1, 3, 17, 40])
 @pytest.mark.parametrize("p", [1, 2])
-def test_db_lb_keogh(L, ctx, Q, p):
+@pytest.mark.parametrize("shape", [0, 2, 3, 4, 5])
+def test_db_lb_keogh(L, ctx, Q, p, shape):
     N, n, w = 777, 96, 9
-    _say(f"db_lb_keogh Q={Q} p={p}")
+    _say(f"db_lb_keogh Q={Q} p={p} shape={shape}")
     X = walks(N, n, 3)
     Ys = walks(Q, n, 4)
     db = L.Db(ctx, to_dev(X))
     env = [R.envelope_naive(Ys[q], w) for q in range(Q)]
     U = to_dev(np.stack([e[0] for e in env]))
     Lo = to_dev(np.stack([e[1] for e in env]))
-    lb = L.lbimp_db_lb_keogh(ctx, db, U, Lo, p).cpu().numpy()
+    L.lbimp_ctx_set_option(ctx, "sweep_shape", shape)
+    try:
+        lb = L.lbimp_db_lb_keogh(ctx, db, U, Lo, p).cpu().numpy()
+    finally:
+        L.lbimp_ctx_set_option(ctx, "sweep_shape", 0)
     for q in range(Q):
         s1, _ = native.lb_many(X, Ys[q], w, p)
         assert_close(lb[q], s1 ** (1.0 / p), lp_scale(X, Ys[q], p), f"db_lb_keogh q={q}")
@@ -317,6 +322,21 @@ def test_nn_search_rw256_full_size_sampled(L, ctx, p):
     assert np.all(st[:, 0] == 100_000)
     # the second pass prunes something on this workload (the point of the method)
     assert st[:, 3].sum() > 0 and st[:, 4].mean() < 0.05 * 100_000
+    db.close()
+
+
+@pytest.mark.parametrize("shape", [2, 3, 4, 5])
+def test_nn_search_sweep_shapes(L, ctx, shape):
+    _say(f"nn_search sweep shape {shape}")
+    X = walks(20_000, 64, 22)
+    Ys = walks(37, 64, 23)
+    db = L.Db(ctx, to_dev(X))
+    L.lbimp_ctx_set_option(ctx, "sweep_shape", shape)
+    try:
+        idx, dist, st = L.lbimp_nn_search(ctx, db, to_dev(Ys), 6, 1, 1, "improved")
+    finally:
+        L.lbimp_ctx_set_option(ctx, "sweep_shape", 0)
+    check_knn(X, Ys[:8], 6, 1, 1, idx.cpu().numpy()[:8], dist.cpu().numpy()[:8], f"shape {shape}")
     db.close()
 
 
