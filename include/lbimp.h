@@ -86,7 +86,10 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *                   one lane per pair; bands with w > 63 always use the anti-diagonal kernel;
  *   "sweep_shape"   0..5 (default 0): tiling of the multi-query LB_Keogh sweep (queries per
  *                   block x candidate tiles per wave: 0 = 16x2, 2 = 8x4, 3 = 32x2, 4 = 16x4,
- *                   5 = 8x2, 1 = 16x2).
+ *                   5 = 8x2, 1 = 16x2);
+ *   "graph"         0/1 (default 1): lbimp_nn_search_ragged captures its launches once as a
+ *                   HIP graph and replays it while the call's pointers and grouping are
+ *                   unchanged (0: launches them directly).
  * Returns LBIMP_E_INVALID for an unknown name or an out-of-range value. */
 int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
 
@@ -142,6 +145,22 @@ int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, in
  * 1 <= k <= 64.  mode: LBIMP_MODE_*. */
 int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                     int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
+
+/* A ragged batch: Q queries of mixed lengths, bands and databases in one call (the search
+ * of Algorithms 2 and 3 for each query; batching changes no result).
+ *   dbs       host [ndb] database handles (lengths may differ);
+ *   queries   device, the queries packed end to end; query q occupies
+ *             queries[offsets[q] .. offsets[q+1]) and its length must equal the length of
+ *             database dbs[db_of[q]];
+ *   offsets   host [Q+1] int64 element offsets; db_of host [Q]; w host [Q] bands;
+ *   idx, dist device [Q][k], row q for query q, as in lbimp_nn_search; stats host [Q] or NULL.
+ * Queries sharing a database and an effective band min(w, n-1) form one group; the groups
+ * run concurrently on the context's streams, ordered after earlier work on its stream and
+ * before later work.  The host arrays may be reused once the call returns.  Calls of
+ * one context must not overlap (they share its workspace); one context per host thread. */
+int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, const float *queries,
+                           const int64_t *offsets, const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p,
+                           int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
 
 #ifdef __cplusplus
 }

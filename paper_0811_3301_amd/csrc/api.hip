@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,6 +43,7 @@ namespace {
 
 constexpr int kStages = 8;
 constexpr int kMaxSeeds = 64;
+constexpr int kPoolStreams = 4;  // concurrent groups of a ragged batch
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -71,6 +74,16 @@ struct lbimp_ctx {
     bool lbi_pipeline = true;   // option "lbi_pipeline"
     bool dtw_low_latency = false;  // option "dtw_group_per_pair" (lbimp_dtw_band only)
     int sweep_shape = 0;           // option "sweep_shape"
+    bool use_graph = true;         // option "graph" (lbimp_nn_search_ragged)
+    // ragged batches: stream pool, captured graph, pinned staging of the grouping metadata
+    hipStream_t graph_stream = nullptr;
+    hipStream_t pool[kPoolStreams] = {};
+    hipEvent_t join_ev[kPoolStreams] = {};
+    hipEvent_t fork_ev = nullptr, enter_ev = nullptr, exit_ev = nullptr, pinned_ev = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_sig = 0;
+    void *pinned = nullptr;
+    size_t pinned_cap = 0;
     hipEvent_t ev[kStages + 1] = {};
 };
 
@@ -87,6 +100,7 @@ static int persistent_grid(const lbimp_ctx *ctx) { return std::max(1, ctx->num_c
 static int reserve(lbimp_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->ws_cap) return LBIMP_OK;
     HIPTRY(hipStreamSynchronize(ctx->stream));
+    if (ctx->graph_stream) HIPTRY(hipStreamSynchronize(ctx->graph_stream));
     if (ctx->ws) HIPTRY(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_cap = 0;
@@ -122,6 +136,214 @@ static void stage_mark(lbimp_ctx *ctx, int i) {
     if (ctx->timing) (void)hipEventRecord(ctx->ev[i], ctx->stream);
 }
 
+// ------------------------------------------------------------------ one homogeneous search
+namespace {
+
+struct Knobs {
+    int seeds;
+    bool lbi_pipeline;
+    int sweep_shape;
+};
+
+struct SearchSpec {  // Q queries of one length against one database
+    const lbimp_db *db;
+    const float *queries;  // device [Q][n]
+    int64_t Q;
+    int w, p, k, mode;
+    int64_t *idx;          // device outputs, row q (or qmap[q]) of [*][k]
+    float *dist;
+    const int64_t *qmap;   // device [Q] output rows, or nullptr for the identity
+    Knobs kn;
+};
+
+struct SearchDims {
+    int n, n4, ldq, wb, qg, S, WL, k, p;
+    int64_t N, Np, Q, Qp, ldres, nw;
+    bool brute, improved, from_minima;
+};
+
+struct SearchBufs {
+    float *Ue, *Le, *S1;
+    int *seeds, *list1, *list2, *counters;
+    u64 *best, *thr, *res, *wmin;
+    long long *prefix;
+};
+
+int dims_of(const SearchSpec &sp, SearchDims &d) {
+    d.n = sp.db->n;
+    d.n4 = (d.n + 3) / 4;
+    d.ldq = d.n4 * 4;
+    d.N = sp.db->N;
+    d.Q = sp.Q;
+    d.k = sp.k;
+    d.p = sp.p;
+    d.wb = band_of(d.n, sp.w);
+    d.Np = (d.N + 63) / 64 * 64;
+    d.qg = sweep_query_group(sp.kn.sweep_shape, sp.Q);
+    d.Qp = (sp.Q + d.qg - 1) / d.qg * d.qg;
+    d.brute = sp.mode == LBIMP_MODE_BRUTE;
+    d.improved = sp.mode == LBIMP_MODE_IMPROVED;
+    d.S = d.brute ? 0 : (int)std::min<int64_t>(std::max(sp.kn.seeds, sp.k), d.N);
+    d.WL = d.improved ? lbi_batch(d.n, d.wb) : 1;
+    if (d.improved && d.WL == 0)
+        return fail(LBIMP_E_UNSUPPORTED, "LB_Improved state for n = %d, w = %d exceeds LDS", d.n, d.wb);
+    d.ldres = d.brute ? std::max<int64_t>(d.N, 1) : d.S + d.N;
+    d.nw = sweep_waves(sp.kn.sweep_shape, d.N, sp.Q);
+    // seeds come from the per-wave minima of the sweep once there are enough of them
+    d.from_minima = !d.brute && d.nw >= 4 * (int64_t)kMaxSeeds;
+    return LBIMP_OK;
+}
+
+void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
+    const bool any = d.N > 0;
+    b.Ue = c.take<float>((size_t)d.Qp * d.ldq);
+    b.Le = c.take<float>((size_t)d.Qp * d.ldq);
+    b.S1 = (d.brute || !any) ? nullptr : c.take<float>((size_t)d.Q * d.Np);
+    b.seeds = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * std::max(d.S, 1));
+    b.best = c.take<u64>((size_t)d.Q);
+    b.thr = c.take<u64>((size_t)d.Q);
+    b.res = (d.k > 1 || !any) ? c.take<u64>((size_t)d.Q * d.ldres) : nullptr;
+    b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.N);
+    b.list2 = (d.improved && any) ? c.take<int>((size_t)d.Q * d.N) : nullptr;
+    b.counters = c.take<int>((size_t)d.Q * 4 + 8);  // cnt1, cnt2, rescnt, abandoned, spare
+    b.prefix = c.take<long long>((size_t)d.Q + 1);
+    b.wmin = (d.from_minima && any) ? c.take<u64>((size_t)d.Q * d.nw) : nullptr;
+}
+
+void fill_stats(const SearchDims &d, int64_t Q, const int *h, const int64_t *ids, lbimp_stats *out) {
+    for (int64_t q = 0; q < Q; ++q) {
+        lbimp_stats &st = out[ids ? ids[q] : q];
+        st.candidates = d.N;
+        st.seeded = d.N ? d.S : 0;
+        st.dtw_abandoned = d.brute ? 0 : h[3 * Q + q];
+        if (d.N == 0) {
+            st = lbimp_stats{0, 0, 0, 0, 0, 0};
+        } else if (d.brute) {
+            st.pruned_keogh = st.pruned_improved = 0;
+            st.dtw_started = d.N;
+        } else {
+            const int64_t c1 = h[q], c2 = d.improved ? h[Q + q] : c1;
+            st.pruned_keogh = d.N - d.S - c1;
+            st.pruned_improved = c1 - c2;
+            st.dtw_started = d.S + c2;
+        }
+    }
+}
+
+}  // namespace
+
+// Enqueue the whole path of one search on stream s (Algorithms 2 and 3 with a seeded threshold).
+static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims &d, const SearchBufs &b,
+                          hipStream_t s, bool mark) {
+    auto stage = [&](int i) {
+        if (mark) stage_mark(ctx, i);
+    };
+    const int64_t Q = d.Q, N = d.N;
+    const int n = d.n, wb = d.wb, p = d.p, k = d.k;
+    int *cnt1 = b.counters, *cnt2 = b.counters + Q, *rescnt = b.counters + 2 * Q, *abandoned = b.counters + 3 * Q;
+    HIPTRY(launch_fill_i32(b.counters, 0, Q * 4 + 8, s));
+    if (N == 0) {  // nothing to search: every slot is empty
+        for (int i = 0; i <= 7; ++i) stage(i);
+        HIPTRY(launch_finalize_k(b.res, 1, rescnt, Q, k, p, sp.idx, sp.dist, sp.qmap, s));
+        stage(8);
+        return LBIMP_OK;
+    }
+    const int grid = persistent_grid(ctx);  // compute units: each persistent kernel sizes its grid by occupancy
+    const u64 *T = k == 1 ? b.best : b.thr;  // pruning threshold keys of the two passes
+    QueryData qd{sp.queries, n, b.Ue, b.Le, d.ldq};
+    const lbimp_db *db = sp.db;
+
+    stage(0);
+    HIPTRY(launch_fill_u64(b.best, kNoKey, Q, s));
+    HIPTRY(launch_fill_u64(b.thr, kNoKey, Q, s));
+    HIPTRY(launch_envelope(sp.queries, Q, d.Qp, n, wb, b.Ue, b.Le, d.ldq, s));
+    stage(1);
+    if (d.brute) {
+        for (int i = 2; i <= 6; ++i) stage(i);
+        HIPTRY(launch_items_prefix(nullptr, N, Q, dtw_batch(n, wb, false), b.prefix, s));
+        PairList all{nullptr, 0, nullptr, N};
+        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, all, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
+                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, nullptr, nullptr, false, false, s));
+    } else {
+        // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
+        HIPTRY(launch_lbk_sweep(p, sp.kn.sweep_shape, db->il, N, d.n4, reinterpret_cast<float4 *>(b.Ue),
+                                reinterpret_cast<float4 *>(b.Le), d.n4, Q, b.S1, d.Np, true, false, b.wmin, s));
+        stage(2);
+        HIPTRY(launch_select_seeds(b.S1, d.Np, N, Q, d.S, b.wmin, d.nw, b.seeds, s));
+        stage(3);
+        // Seeds: few pairs per query on the critical path, so a group of lanes per pair (low
+        // latency); they run to completion, their DTWs finishing together.
+        HIPTRY(launch_items_prefix(nullptr, d.S, Q, dtw_batch(n, wb, true), b.prefix, s));
+        PairList seedl{b.seeds, d.S, nullptr, d.S};
+        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, seedl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
+                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, true, s));
+        if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, b.thr, s));
+        stage(4);
+        HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
+        stage(5);
+        PairList dl{b.list1, N, cnt1, 0};
+        if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
+            HIPTRY(launch_items_prefix(cnt1, 0, Q, d.WL, b.prefix, s));
+            HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, b.S1, d.Np, b.prefix, Q, nullptr, grid,
+                              T, b.list2, N, cnt2, nullptr, sp.kn.lbi_pipeline, s));
+            dl = PairList{b.list2, N, cnt2, 0};
+        }
+        stage(6);
+        HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, false), b.prefix, s));
+        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
+                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, false, s));
+    }
+    stage(7);
+    if (k == 1)
+        HIPTRY(launch_finalize1(b.best, Q, p, sp.idx, sp.dist, sp.qmap, s));
+    else
+        HIPTRY(launch_finalize_k(b.res, d.ldres, rescnt, Q, k, p, sp.idx, sp.dist, sp.qmap, s));
+    stage(8);
+    return LBIMP_OK;
+}
+
+static Knobs ctx_knobs(const lbimp_ctx *ctx) { return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape}; }
+
+static int check_search(int64_t Q, int32_t n, int32_t w, int32_t p, int32_t k, int32_t mode) {
+    if (int r = check_shape(Q, n, w, p)) return r;
+    if (k < 1 || k > 64) return fail(LBIMP_E_INVALID, "k = %d outside [1, 64]", k);
+    if (mode < LBIMP_MODE_BRUTE || mode > LBIMP_MODE_IMPROVED) return fail(LBIMP_E_INVALID, "unknown mode %d", mode);
+    return LBIMP_OK;
+}
+
+static int reserve_pinned(lbimp_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->pinned_cap) {
+        if (ctx->pinned_ev) HIPTRY(hipEventSynchronize(ctx->pinned_ev));  // the last upload has read it
+        return LBIMP_OK;
+    }
+    if (ctx->pinned_ev) HIPTRY(hipEventSynchronize(ctx->pinned_ev));
+    if (ctx->pinned) HIPTRY(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_cap = 0;
+    size_t cap = align_up(bytes + bytes / 4, 1 << 16);
+    if (hipHostMalloc(&ctx->pinned, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->pinned = nullptr;
+        return fail(LBIMP_E_NOMEM, "pinned staging allocation of %zu bytes failed", cap);
+    }
+    ctx->pinned_cap = cap;
+    return LBIMP_OK;
+}
+
+static int ensure_pool(lbimp_ctx *ctx) {
+    if (ctx->graph_stream) return LBIMP_OK;
+    HIPTRY(hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
+    for (int i = 0; i < kPoolStreams; ++i) {
+        HIPTRY(hipStreamCreateWithFlags(&ctx->pool[i], hipStreamNonBlocking));
+        HIPTRY(hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming));
+    }
+    HIPTRY(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+    HIPTRY(hipEventCreateWithFlags(&ctx->enter_ev, hipEventDisableTiming));
+    HIPTRY(hipEventCreateWithFlags(&ctx->exit_ev, hipEventDisableTiming));
+    HIPTRY(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
+    return LBIMP_OK;
+}
+
 extern "C" {
 
 const char *lbimp_last_error(void) { return g_err.c_str(); }
@@ -153,8 +375,18 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->graph_stream) (void)hipStreamSynchronize(ctx->graph_stream);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    for (int i = 0; i < kPoolStreams; ++i) {
+        if (ctx->pool[i]) (void)hipStreamDestroy(ctx->pool[i]);
+        if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
+    }
+    for (hipEvent_t e : {ctx->fork_ev, ctx->enter_ev, ctx->exit_ev, ctx->pinned_ev})
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->ws) (void)hipFree(ctx->ws);
     delete ctx;
 }
@@ -177,6 +409,8 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         ctx->lbi_pipeline = value != 0;
     } else if (!strcmp(name, "dtw_group_per_pair")) {
         ctx->dtw_low_latency = value != 0;
+    } else if (!strcmp(name, "graph")) {
+        ctx->use_graph = value != 0;
     } else if (!strcmp(name, "sweep_shape")) {
         if (value < 0 || value > 5) return fail(LBIMP_E_INVALID, "sweep_shape must be in [0, 5]");
         ctx->sweep_shape = (int)value;
@@ -375,150 +609,181 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     if (int r = check_ctx(ctx)) return r;
     if (!db) return fail(LBIMP_E_INVALID, "null database");
     if (db->device != ctx->device) return fail(LBIMP_E_INVALID, "database lives on another device");
-    if (int r = check_shape(Q, db->n, w, p)) return r;
-    if (k < 1 || k > 64) return fail(LBIMP_E_INVALID, "k = %d outside [1, 64]", k);
-    if (mode < LBIMP_MODE_BRUTE || mode > LBIMP_MODE_IMPROVED) return fail(LBIMP_E_INVALID, "unknown mode %d", mode);
+    if (int r = check_search(Q, db->n, w, p, k, mode)) return r;
     if (Q == 0) return LBIMP_OK;
     if (!queries || !idx || !dist) return fail(LBIMP_E_INVALID, "null pointer");
-
-    const int n = db->n, n4 = (n + 3) / 4, ldq = n4 * 4;
-    const int64_t N = db->N;
-    const int wb = band_of(n, w);
-    const int64_t Np = (N + 63) / 64 * 64;
-    const int qg = sweep_query_group(ctx->sweep_shape, Q);
-    const int64_t Qp = (Q + qg - 1) / qg * qg;
-    const bool brute = mode == LBIMP_MODE_BRUTE;
-    const bool improved = mode == LBIMP_MODE_IMPROVED;
-    const int S = brute ? 0 : (int)std::min<int64_t>(std::max(ctx->seeds, k), N);
-    const int WL = improved ? lbi_batch(n, wb) : 1;
-    if (improved && WL == 0)
-        return fail(LBIMP_E_UNSUPPORTED, "LB_Improved state for n = %d, w = %d exceeds LDS", n, wb);
-    const int64_t ldres = brute ? N : S + N;
-    hipStream_t s = ctx->stream;
-
-    if (N == 0) {  // nothing to search: every slot is empty
-        Carver cv{nullptr};
-        cv.take<u64>((size_t)Q);
-        cv.take<int>((size_t)Q);
-        if (int r = reserve(ctx, cv.off)) return r;
-        Carver c2{static_cast<char *>(ctx->ws)};
-        u64 *res = c2.take<u64>((size_t)Q);
-        int *rescnt = c2.take<int>((size_t)Q);
-        HIPTRY(launch_fill_i32(rescnt, 0, Q, s));
-        HIPTRY(launch_finalize_k(res, 1, rescnt, Q, k, p, idx, dist, s));
-        if (stats) {
-            HIPTRY(hipStreamSynchronize(s));
-            for (int64_t q = 0; q < Q; ++q) stats[q] = lbimp_stats{0, 0, 0, 0, 0, 0};
-        }
-        return LBIMP_OK;
-    }
-
-    // ---- workspace layout
-    // Seeds come from the per-wave minima of the sweep once there are enough of them.
-    const int64_t nw = sweep_waves(ctx->sweep_shape, N, Q);
-    const bool seeds_from_minima = !brute && nw >= 4 * (int64_t)kMaxSeeds;
-    auto layout = [&](Carver &c, float *&Ue, float *&Le, float *&S1, int *&seeds, u64 *&best, u64 *&thr, u64 *&res,
-                      int *&list1, int *&list2, int *&counters, long long *&prefix, u64 *&wmin) {
-        Ue = c.take<float>((size_t)Qp * ldq);
-        Le = c.take<float>((size_t)Qp * ldq);
-        S1 = brute ? nullptr : c.take<float>((size_t)Q * Np);
-        seeds = brute ? nullptr : c.take<int>((size_t)Q * std::max(S, 1));
-        best = c.take<u64>((size_t)Q);
-        thr = c.take<u64>((size_t)Q);
-        res = k > 1 ? c.take<u64>((size_t)Q * ldres) : nullptr;
-        list1 = brute ? nullptr : c.take<int>((size_t)Q * N);
-        list2 = improved ? c.take<int>((size_t)Q * N) : nullptr;
-        counters = c.take<int>((size_t)Q * 4 + 8);  // cnt1, cnt2, rescnt, abandoned, item counters
-        prefix = c.take<long long>((size_t)Q + 1);
-        wmin = seeds_from_minima ? c.take<u64>((size_t)Q * nw) : nullptr;
-    };
-    float *Ue, *Le, *S1;
-    int *seeds, *list1, *list2, *counters;
-    u64 *best, *thr, *res, *wmin;
-    long long *prefix;
+    SearchSpec sp{db, queries, Q, w, p, k, mode, idx, dist, nullptr, ctx_knobs(ctx)};
+    SearchDims d;
+    if (int r = dims_of(sp, d)) return r;
+    SearchBufs bufs;
     {
         Carver cv{nullptr};
-        layout(cv, Ue, Le, S1, seeds, best, thr, res, list1, list2, counters, prefix, wmin);
+        layout(cv, d, bufs);
         if (int r = reserve(ctx, cv.off)) return r;
         Carver c2{static_cast<char *>(ctx->ws)};
-        layout(c2, Ue, Le, S1, seeds, best, thr, res, list1, list2, counters, prefix, wmin);
+        layout(c2, d, bufs);
     }
-    int *cnt1 = counters, *cnt2 = counters + Q, *rescnt = counters + 2 * Q, *abandoned = counters + 3 * Q;
-    int *ctr = counters + 4 * Q;
-    const int grid = persistent_grid(ctx);  // compute units: each persistent kernel sizes its grid by occupancy
-    const u64 *T = k == 1 ? best : thr;  // pruning threshold keys of the two passes
-    QueryData qd{queries, n, Ue, Le, ldq};
-
     ctx->timed_valid = false;
-    stage_mark(ctx, 0);
-    HIPTRY(launch_fill_i32(counters, 0, Q * 4 + 8, s));
-    HIPTRY(launch_fill_u64(best, kNoKey, Q, s));
-    HIPTRY(launch_fill_u64(thr, kNoKey, Q, s));
-    HIPTRY(launch_envelope(queries, Q, Qp, n, wb, Ue, Le, ldq, s));
-    stage_mark(ctx, 1);
-
-    if (brute) {
-        for (int i = 2; i <= 5; ++i) stage_mark(ctx, i);
-        stage_mark(ctx, 6);
-        HIPTRY(launch_items_prefix(nullptr, N, Q, dtw_batch(n, wb, false), prefix, s));
-        PairList all{nullptr, 0, nullptr, N};
-        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, all, prefix, Q, ctr + 0, grid, k == 1 ? best : nullptr,
-                          k == 1 ? nullptr : thr, res, ldres, rescnt, nullptr, nullptr, false, false, s));
-    } else {
-        // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
-        HIPTRY(launch_lbk_sweep(p, ctx->sweep_shape, db->il, N, n4, reinterpret_cast<float4 *>(Ue), reinterpret_cast<float4 *>(Le),
-                                n4, Q, S1, Np, true, false, wmin, s));
-        stage_mark(ctx, 2);
-        HIPTRY(launch_select_seeds(S1, Np, N, Q, S, wmin, nw, seeds, s));
-        stage_mark(ctx, 3);
-        // Seeds: few pairs per query on the critical path, so a group of lanes per pair (low
-        // latency); they run to completion, their DTWs finishing together.
-        HIPTRY(launch_items_prefix(nullptr, S, Q, dtw_batch(n, wb, true), prefix, s));
-        PairList sp{seeds, S, nullptr, S};
-        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, sp, prefix, Q, ctr + 0, grid, k == 1 ? best : nullptr,
-                          k == 1 ? nullptr : thr, res, ldres, rescnt, abandoned, nullptr, false, true, s));
-        if (k > 1) HIPTRY(launch_kth_key(res, ldres, rescnt, Q, k, thr, s));
-        stage_mark(ctx, 4);
-        HIPTRY(launch_compact(S1, Np, N, Q, T, list1, N, cnt1, s));
-        stage_mark(ctx, 5);
-        PairList dl{list1, N, cnt1, 0};
-        if (improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
-            HIPTRY(launch_items_prefix(cnt1, 0, Q, WL, prefix, s));
-            HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, S1, Np, prefix, Q, ctr + 1, grid, T,
-                              list2, N, cnt2, nullptr, ctx->lbi_pipeline, s));
-            dl = PairList{list2, N, cnt2, 0};
-        }
-        stage_mark(ctx, 6);
-        HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, false), prefix, s));
-        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, prefix, Q, ctr + 2, grid, k == 1 ? best : nullptr,
-                          k == 1 ? nullptr : thr, res, ldres, rescnt, abandoned, nullptr, true, false, s));
-    }
-    stage_mark(ctx, 7);
-    if (k == 1)
-        HIPTRY(launch_finalize1(best, Q, p, idx, dist, s));
-    else
-        HIPTRY(launch_finalize_k(res, ldres, rescnt, Q, k, p, idx, dist, s));
-    stage_mark(ctx, 8);
+    if (int r = enqueue_search(ctx, sp, d, bufs, ctx->stream, true)) return r;
     ctx->timed_valid = ctx->timing;
-
     if (stats) {
         std::vector<int> h((size_t)Q * 4);
-        HIPTRY(hipMemcpyAsync(h.data(), counters, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s));
-        HIPTRY(hipStreamSynchronize(s));
-        for (int64_t q = 0; q < Q; ++q) {
-            lbimp_stats &st = stats[q];
-            st.candidates = N;
-            st.seeded = S;
-            st.dtw_abandoned = brute ? 0 : h[3 * Q + q];
-            if (brute) {
-                st.pruned_keogh = st.pruned_improved = 0;
-                st.dtw_started = N;
-            } else {
-                const int64_t c1 = h[q], c2 = improved ? h[Q + q] : c1;
-                st.pruned_keogh = N - S - c1;
-                st.pruned_improved = c1 - c2;
-                st.dtw_started = S + c2;
+        HIPTRY(hipMemcpyAsync(h.data(), bufs.counters, sizeof(int) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+        HIPTRY(hipStreamSynchronize(ctx->stream));
+        fill_stats(d, Q, h.data(), nullptr, stats);
+    }
+    return LBIMP_OK;
+}
+
+int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, const float *queries,
+                           const int64_t *offsets, const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p,
+                           int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats) {
+    if (int r = check_ctx(ctx)) return r;
+    if (Q < 0) return fail(LBIMP_E_INVALID, "negative query count");
+    if (Q == 0) return LBIMP_OK;
+    if (!dbs || ndb < 1 || !queries || !offsets || !db_of || !w || !idx || !dist)
+        return fail(LBIMP_E_INVALID, "null pointer or no database");
+    for (int i = 0; i < ndb; ++i) {
+        if (!dbs[i]) return fail(LBIMP_E_INVALID, "null database %d", i);
+        if (dbs[i]->device != ctx->device) return fail(LBIMP_E_INVALID, "database %d lives on another device", i);
+    }
+    // group the queries by (database, effective band); every group is one homogeneous search
+    std::map<std::pair<int, int>, std::vector<int64_t>> groups;
+    for (int64_t q = 0; q < Q; ++q) {
+        const int b = db_of[q];
+        if (b < 0 || b >= ndb) return fail(LBIMP_E_INVALID, "query %lld: database %d of %d", (long long)q, b, ndb);
+        const int64_t len = offsets[q + 1] - offsets[q];
+        if (offsets[q] < 0 || len != dbs[b]->n)
+            return fail(LBIMP_E_INVALID, "query %lld: length %lld, database length %d", (long long)q, (long long)len,
+                        dbs[b]->n);
+        if (int r = check_search(1, dbs[b]->n, w[q], p, k, mode)) return r;
+        groups[{b, band_of(dbs[b]->n, w[q])}].push_back(q);
+    }
+    const int G = (int)groups.size();
+    std::vector<SearchSpec> specs;
+    std::vector<SearchDims> dims(G);
+    std::vector<SearchBufs> bufs(G);
+    std::vector<float *> qbuf(G);
+    std::vector<int64_t *> qmap(G), qsrc(G);
+    specs.reserve(G);
+    for (auto &kv : groups) {
+        const int64_t Qg = (int64_t)kv.second.size();
+        specs.push_back(SearchSpec{dbs[kv.first.first], nullptr, Qg, kv.first.second, p, k, mode, idx, dist, nullptr,
+                                   ctx_knobs(ctx)});
+        if (int r = dims_of(specs.back(), dims[specs.size() - 1])) return r;
+    }
+    // workspace: [metadata: per group query ids and source offsets][per group: gathered queries + search]
+    size_t meta_elems = 0;
+    for (int g = 0; g < G; ++g) meta_elems += 2 * (size_t)specs[g].Q;
+    int64_t *meta = nullptr;
+    auto carve = [&](Carver &c) {
+        meta = c.take<int64_t>(meta_elems);  // per group: query ids, then source offsets, packed
+        size_t o = 0;
+        for (int g = 0; g < G; ++g) {
+            qmap[g] = meta ? meta + o : nullptr;
+            qsrc[g] = meta ? meta + o + specs[g].Q : nullptr;
+            o += 2 * (size_t)specs[g].Q;
+        }
+        for (int g = 0; g < G; ++g) {
+            qbuf[g] = c.take<float>((size_t)specs[g].Q * dims[g].n);
+            layout(c, dims[g], bufs[g]);
+        }
+    };
+    {
+        Carver cv{nullptr};
+        carve(cv);
+        if (int r = reserve(ctx, cv.off)) return r;
+        Carver c2{static_cast<char *>(ctx->ws)};
+        carve(c2);
+    }
+    // upload the metadata through a pinned staging buffer (outside any captured graph)
+    if (int r = ensure_pool(ctx)) return r;
+    if (int r = reserve_pinned(ctx, meta_elems * sizeof(int64_t))) return r;
+    {
+        int64_t *h = static_cast<int64_t *>(ctx->pinned);
+        size_t o = 0;
+        for (auto &kv : groups) {
+            for (int64_t q : kv.second) h[o++] = q;
+            for (int64_t q : kv.second) h[o++] = offsets[q];
+        }
+        HIPTRY(hipMemcpyAsync(meta, h, meta_elems * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        HIPTRY(hipEventRecord(ctx->pinned_ev, ctx->stream));
+    }
+    for (int g = 0; g < G; ++g) {
+        specs[g].queries = qbuf[g];
+        specs[g].qmap = qmap[g];
+    }
+    // the groups run concurrently on the context's stream pool, captured once as a graph and
+    // replayed while the call's signature (pointers, shapes, grouping, workspace) is unchanged
+    auto enqueue_all = [&](hipStream_t main) -> int {
+        HIPTRY(hipEventRecord(ctx->fork_ev, main));
+        for (int i = 0; i < kPoolStreams; ++i) HIPTRY(hipStreamWaitEvent(ctx->pool[i], ctx->fork_ev, 0));
+        for (int g = 0; g < G; ++g) {
+            hipStream_t sg = ctx->pool[g % kPoolStreams];
+            HIPTRY(launch_gather_rows(queries, qsrc[g], dims[g].n, specs[g].Q, qbuf[g], sg));
+            if (int r = enqueue_search(ctx, specs[g], dims[g], bufs[g], sg, false)) return r;
+        }
+        for (int i = 0; i < kPoolStreams; ++i) {
+            HIPTRY(hipEventRecord(ctx->join_ev[i], ctx->pool[i]));
+            HIPTRY(hipStreamWaitEvent(main, ctx->join_ev[i], 0));
+        }
+        return LBIMP_OK;
+    };
+    uint64_t sig = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
+    mix((uint64_t)(uintptr_t)ctx->ws);
+    mix((uint64_t)(uintptr_t)queries);
+    mix((uint64_t)(uintptr_t)idx);
+    mix((uint64_t)(uintptr_t)dist);
+    mix((uint64_t)Q);
+    mix((uint64_t)(p * 131 + k * 7 + mode));
+    for (int g = 0; g < G; ++g) {
+        const lbimp_db *db = specs[g].db;  // a database freed and recreated may reuse an address
+        mix((uint64_t)(uintptr_t)db);
+        mix((uint64_t)(uintptr_t)db->rows);
+        mix((uint64_t)(uintptr_t)db->il);
+        mix((uint64_t)db->N);
+        mix((uint64_t)db->n);
+        mix((uint64_t)specs[g].Q);
+        mix((uint64_t)specs[g].w);
+        mix((uint64_t)(specs[g].kn.seeds * 1000 + specs[g].kn.sweep_shape * 10 + specs[g].kn.lbi_pipeline));
+    }
+    HIPTRY(hipEventRecord(ctx->enter_ev, ctx->stream));
+    HIPTRY(hipStreamWaitEvent(ctx->graph_stream, ctx->enter_ev, 0));
+    if (ctx->use_graph) {
+        if (!ctx->graph_exec || ctx->graph_sig != sig) {
+            if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+            ctx->graph_exec = nullptr;
+            hipGraph_t graph = nullptr;
+            HIPTRY(hipStreamBeginCapture(ctx->graph_stream, hipStreamCaptureModeRelaxed));
+            int r = enqueue_all(ctx->graph_stream);
+            hipError_t e = hipStreamEndCapture(ctx->graph_stream, &graph);
+            if (r) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return r;
             }
+            if (e != hipSuccess) return fail(LBIMP_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                ctx->graph_exec = nullptr;
+                return fail(LBIMP_E_DEVICE, "graph instantiation: %s", hipGetErrorString(e));
+            }
+            ctx->graph_sig = sig;
+        }
+        HIPTRY(hipGraphLaunch(ctx->graph_exec, ctx->graph_stream));
+    } else {
+        if (int r = enqueue_all(ctx->graph_stream)) return r;
+    }
+    HIPTRY(hipEventRecord(ctx->exit_ev, ctx->graph_stream));
+    HIPTRY(hipStreamWaitEvent(ctx->stream, ctx->exit_ev, 0));
+    if (stats) {
+        HIPTRY(hipStreamSynchronize(ctx->stream));
+        for (int g = 0; g < G; ++g) {
+            std::vector<int> h((size_t)specs[g].Q * 4);
+            HIPTRY(hipMemcpy(h.data(), bufs[g].counters, sizeof(int) * h.size(), hipMemcpyDeviceToHost));
+            const std::vector<int64_t> &ids = std::next(groups.begin(), g)->second;
+            fill_stats(dims[g], specs[g].Q, h.data(), ids.data(), stats);
         }
     }
     return LBIMP_OK;

@@ -283,30 +283,48 @@ __device__ __forceinline__ float key_root(u64 key, int p) {
 }
 
 __global__ void k_finalize1(const u64 *__restrict__ best, int64_t Q, int p, int64_t *__restrict__ idx,
-                            float *__restrict__ dist) {
+                            float *__restrict__ dist, const int64_t *__restrict__ qmap) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= Q) return;
     const u64 key = best[q];
+    const int64_t row = qmap ? qmap[q] : q;
     if (key == kNoKey) {
-        idx[q] = -1;
-        dist[q] = kInf;
+        idx[row] = -1;
+        dist[row] = kInf;
     } else {
-        idx[q] = (int64_t)(key & 0xffffffffu);
-        dist[q] = key_root(key, p);
+        idx[row] = (int64_t)(key & 0xffffffffu);
+        dist[row] = key_root(key, p);
     }
 }
 
 hipError_t launch_finalize1(const unsigned long long *best, int64_t Q, int p, int64_t *idx, float *dist,
-                            hipStream_t s) {
+                            const int64_t *qmap, hipStream_t s) {
     if (Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize1, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s, best, Q, p, idx, dist);
+    hipLaunchKernelGGL(k_finalize1, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s, best, Q, p, idx, dist, qmap);
+    return hipGetLastError();
+}
+
+__global__ void k_gather_rows(const float *__restrict__ src, const int64_t *__restrict__ off, int n, int64_t total,
+                              float *__restrict__ dst) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int64_t j = g / n;
+    const int i = (int)(g - j * n);
+    dst[g] = src[off[j] + i];
+}
+
+hipError_t launch_gather_rows(const float *src, const int64_t *off, int n, int64_t count, float *dst, hipStream_t s) {
+    const int64_t total = count * n;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, off, n, total, dst);
     return hipGetLastError();
 }
 
 // k rounds of a block-wide minimum; each selected key is removed before the next round.
 __global__ __launch_bounds__(256) void k_finalize_k(u64 *__restrict__ res, int64_t ldres,
                                                     const int *__restrict__ rescnt, int k, int p,
-                                                    int64_t *__restrict__ idx, float *__restrict__ dist) {
+                                                    int64_t *__restrict__ idx, float *__restrict__ dist,
+                                                    const int64_t *__restrict__ qmap) {
     __shared__ u64 red[256];
     const int64_t q = blockIdx.x;
     const int cnt = rescnt[q];
@@ -327,17 +345,18 @@ __global__ __launch_bounds__(256) void k_finalize_k(u64 *__restrict__ res, int64
                 if (r[t] == best) r[t] = kNoKey;
         }
         if (threadIdx.x == 0) {
-            idx[q * k + round] = best == kNoKey ? -1 : (int64_t)(best & 0xffffffffu);
-            dist[q * k + round] = best == kNoKey ? kInf : key_root(best, p);
+            const int64_t row = qmap ? qmap[q] : q;
+            idx[row * k + round] = best == kNoKey ? -1 : (int64_t)(best & 0xffffffffu);
+            dist[row * k + round] = best == kNoKey ? kInf : key_root(best, p);
         }
         __syncthreads();
     }
 }
 
 hipError_t launch_finalize_k(unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k, int p,
-                             int64_t *idx, float *dist, hipStream_t s) {
+                             int64_t *idx, float *dist, const int64_t *qmap, hipStream_t s) {
     if (Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize_k, dim3((unsigned)Q), dim3(256), 0, s, res, ldres, rescnt, k, p, idx, dist);
+    hipLaunchKernelGGL(k_finalize_k, dim3((unsigned)Q), dim3(256), 0, s, res, ldres, rescnt, k, p, idx, dist, qmap);
     return hipGetLastError();
 }
 

@@ -53,6 +53,9 @@ SIGNATURES = {
     "lbimp_dtw_band": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _i32, _i32, _vp]),
     "lbimp_nn_search": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp,
                                        ctypes.POINTER(LbimpStats)]),
+    "lbimp_nn_search_ragged": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i32, _vp, ctypes.POINTER(_i64),
+                                              ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i64, _i32, _i32, _i32,
+                                              _vp, _vp, ctypes.POINTER(LbimpStats)]),
 }
 
 _lib = None
@@ -236,8 +239,36 @@ def lbimp_nn_search(ctx: Ctx, db: Db, queries: torch.Tensor, w: int, p: int, k: 
     st = (LbimpStats * max(Q, 1))() if stats else None
     _check(_lib.lbimp_nn_search(ctx.sync_stream(), db.h, _dev(queries, "queries") if Q else None, Q, w, p, k, mode,
                                 _dev(idx, "idx", torch.int64), _dev(dist, "dist"), st), "lbimp_nn_search")
-    out_stats = None
-    if stats:
-        out_stats = np.array([[getattr(s, f) for f in STATS_FIELDS] for s in st[:Q]], dtype=np.int64).reshape(
-            Q, len(STATS_FIELDS))
-    return idx, dist, out_stats
+    return idx, dist, (_stats_array(st, Q) if stats else None)
+
+
+def _stats_array(st, Q):
+    return np.array([[getattr(s, f) for f in STATS_FIELDS] for s in st[:Q]], dtype=np.int64).reshape(
+        Q, len(STATS_FIELDS))
+
+
+def lbimp_nn_search_ragged(ctx: Ctx, dbs, queries: torch.Tensor, offsets, db_of, w, p: int, k: int = 1,
+                           mode="improved", idx=None, dist=None, stats: bool = True):
+    """Ragged batch: `queries` is a 1-D device tensor holding the queries end to end, query q at
+    [offsets[q], offsets[q+1]); db_of[q] indexes `dbs`; w is one band or one per query.
+    Returns (idx [Q][k], dist [Q][k], stats) as lbimp_nn_search does."""
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    Q = off.shape[0] - 1
+    if Q < 0:
+        raise ValueError("offsets must hold Q + 1 entries")
+    dof = np.ascontiguousarray(db_of, dtype=np.int32)
+    wq = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.int32), (Q,)))
+    if dof.shape != (Q,):
+        raise ValueError("db_of must hold Q entries")
+    idx = _out(idx, (Q, k), torch.int64, queries)
+    dist = _out(dist, (Q, k), torch.float32, queries)
+    handles = (_vp * max(len(dbs), 1))(*[d.h for d in dbs])
+    st = (LbimpStats * max(Q, 1))() if stats else None
+    _check(_lib.lbimp_nn_search_ragged(
+        ctx.sync_stream(), handles, len(dbs), _dev(queries, "queries") if queries.numel() else None,
+        off.ctypes.data_as(ctypes.POINTER(_i64)), dof.ctypes.data_as(ctypes.POINTER(_i32)),
+        wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p, k, mode, _dev(idx, "idx", torch.int64), _dev(dist, "dist"),
+        st), "lbimp_nn_search_ragged")
+    return idx, dist, (_stats_array(st, Q) if stats else None)
