@@ -159,17 +159,18 @@ struct SearchSpec {  // Q queries of one length against one database
 struct SearchDims {
     int n, n4, ldq, wb, qg, S, WL, k, p;
     int64_t N, Np, Q, Qp, ldres, nw;
+    size_t ring_bytes;  // strip-boundary scratch of the wide-band DTW
     bool brute, improved, from_minima;
 };
 
 struct SearchBufs {
-    float *Ue, *Le, *S1;
+    float *Ue, *Le, *S1, *ring;
     int *seeds, *list1, *list2, *counters;
     u64 *best, *thr, *res, *wmin;
     long long *prefix;
 };
 
-int dims_of(const SearchSpec &sp, SearchDims &d) {
+int dims_of(const SearchSpec &sp, int num_cu, SearchDims &d) {
     d.n = sp.db->n;
     d.n4 = (d.n + 3) / 4;
     d.ldq = d.n4 * 4;
@@ -191,6 +192,7 @@ int dims_of(const SearchSpec &sp, SearchDims &d) {
     d.nw = sweep_waves(sp.kn.sweep_shape, d.N, sp.Q);
     // seeds come from the per-wave minima of the sweep once there are enough of them
     d.from_minima = !d.brute && d.nw >= 4 * (int64_t)kMaxSeeds;
+    d.ring_bytes = dtw_strip_scratch(d.p, d.n, d.wb, num_cu);
     return LBIMP_OK;
 }
 
@@ -208,6 +210,7 @@ void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
     b.counters = c.take<int>((size_t)d.Q * 4 + 8);  // cnt1, cnt2, rescnt, abandoned, spare
     b.prefix = c.take<long long>((size_t)d.Q + 1);
     b.wmin = (d.from_minima && any) ? c.take<u64>((size_t)d.Q * d.nw) : nullptr;
+    b.ring = (d.ring_bytes && any) ? c.take<float>(d.ring_bytes / sizeof(float)) : nullptr;
 }
 
 void fill_stats(const SearchDims &d, int64_t Q, const int *h, const int64_t *ids, lbimp_stats *out) {
@@ -263,7 +266,8 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         HIPTRY(launch_items_prefix(nullptr, N, Q, dtw_batch(n, wb, false), b.prefix, s));
         PairList all{nullptr, 0, nullptr, N};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, all, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, nullptr, nullptr, false, false, s));
+                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, nullptr, nullptr, false, false, b.ring,
+                          d.ring_bytes, s));
     } else {
         // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
         HIPTRY(launch_lbk_sweep(p, sp.kn.sweep_shape, db->il, N, d.n4, reinterpret_cast<float4 *>(b.Ue),
@@ -276,7 +280,8 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         HIPTRY(launch_items_prefix(nullptr, d.S, Q, dtw_batch(n, wb, true), b.prefix, s));
         PairList seedl{b.seeds, d.S, nullptr, d.S};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, seedl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, true, s));
+                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, true, b.ring,
+                          d.ring_bytes, s));
         if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, b.thr, s));
         stage(4);
         HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
@@ -291,7 +296,8 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         stage(6);
         HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, false), b.prefix, s));
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, false, s));
+                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, false, b.ring,
+                          d.ring_bytes, s));
     }
     stage(7);
     if (k == 1)
@@ -582,25 +588,28 @@ int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, in
     if (N == 0) return LBIMP_OK;
     if (!x || !y || !dist) return fail(LBIMP_E_INVALID, "null pointer");
     const int wb = band_of(n, w);
+    const bool ll = ctx->dtw_low_latency;
+    const size_t ring_bytes = ll ? 0 : dtw_strip_scratch(p, n, wb, ctx->num_cu);
     Carver cv{nullptr};
     cv.take<long long>(2);
     cv.take<int>(1);
     cv.take<u64>(1);
+    cv.take<float>(ring_bytes / sizeof(float));
     if (int r = reserve(ctx, cv.off)) return r;
     Carver c2{static_cast<char *>(ctx->ws)};
     long long *prefix = c2.take<long long>(2);
     int *ctr = c2.take<int>(1);
     u64 *nothr = c2.take<u64>(1);
+    float *ring = c2.take<float>(ring_bytes / sizeof(float));
     hipStream_t s = ctx->stream;
     HIPTRY(launch_fill_i32(ctr, 0, 1, s));
     HIPTRY(launch_fill_u64(nothr, kNoKey, 1, s));
-    const bool ll = ctx->dtw_low_latency;
     HIPTRY(launch_items_prefix(nullptr, N, 1, dtw_batch(n, wb, ll), prefix, s));
     QueryData qd{y, n, nullptr, nullptr, 0};
     PairList pl{nullptr, 0, nullptr, N};
     // no threshold: nothing is abandoned and nothing appended (out_root receives every distance)
     HIPTRY(launch_dtw(p, x, n, wb, qd, pl, prefix, 1, ctr, persistent_grid(ctx), nullptr, nothr, nullptr, 0,
-                      nullptr, nullptr, dist, false, ll, s));
+                      nullptr, nullptr, dist, false, ll, ring, ring_bytes, s));
     return LBIMP_OK;
 }
 
@@ -614,7 +623,7 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     if (!queries || !idx || !dist) return fail(LBIMP_E_INVALID, "null pointer");
     SearchSpec sp{db, queries, Q, w, p, k, mode, idx, dist, nullptr, ctx_knobs(ctx)};
     SearchDims d;
-    if (int r = dims_of(sp, d)) return r;
+    if (int r = dims_of(sp, ctx->num_cu, d)) return r;
     SearchBufs bufs;
     {
         Carver cv{nullptr};
@@ -670,7 +679,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         const int64_t Qg = (int64_t)kv.second.size();
         specs.push_back(SearchSpec{dbs[kv.first.first], nullptr, Qg, kv.first.second, p, k, mode, idx, dist, nullptr,
                                    ctx_knobs(ctx)});
-        if (int r = dims_of(specs.back(), dims[specs.size() - 1])) return r;
+        if (int r = dims_of(specs.back(), ctx->num_cu, dims[specs.size() - 1])) return r;
     }
     // workspace: [metadata: per group query ids and source offsets][per group: gathered queries + search]
     size_t meta_elems = 0;

@@ -12,6 +12,10 @@ Workloads (each stands in for a data set of the paper's experiments, Sec. 10):
   polygons, a synthetic stand-in for the shape archives of Sec. 10.2, which are
   not available here.
 * ``poisson_arrivals``: request arrival times for the serving loop.
+* ``make_ragged_workload``: a batch of random-walk queries of mixed lengths and
+  bands, each length with its own database (uneven batches; not a paper experiment).
+* ``make_serving_workload``: a request stream over two resident databases (serving;
+  not a paper experiment).
 
 Seeds follow ``SeedSequence([8113301, config_id, role, *extra])``, role 0 = database,
 1 = queries, 2 = arrivals and per-request draws.
@@ -124,3 +128,51 @@ def make_workload(name: str, N: int | None = None, Q: int | None = None):
         db = shape_signatures(N, n, rng(spec["config_id"], ROLE_DB))
         qs = shape_signatures(Q, n, rng(spec["config_id"], ROLE_QUERY))
     return db, qs
+
+
+RAGGED_LENGTHS = (64, 128, 256, 512, 1024)
+RAGGED_FRACTIONS = (0.05, 0.1, 0.2)
+
+
+def make_ragged_workload(Q: int = 4096, N: int = 20_000, lengths=RAGGED_LENGTHS, fractions=RAGGED_FRACTIONS,
+                         config_id: int = 4):
+    """Uneven batch: Q random-walk queries, length uniform over ``lengths``, band
+    w = round(f * n) with f uniform over ``fractions``; one random-walk database of N
+    series per length.  Returns (dbs, queries, db_of, w): dbs[i] is [N][lengths[i]],
+    queries a list of 1-D arrays, db_of[q] the database of query q."""
+    r = rng(config_id, ROLE_QUERY)
+    db_of = r.integers(0, len(lengths), Q).astype(np.int32)
+    frac = r.integers(0, len(fractions), Q)
+    w = np.array([band_from_fraction(lengths[b], fractions[f]) for b, f in zip(db_of, frac)], dtype=np.int32)
+    dbs = [random_walk(N, n, rng(config_id, ROLE_DB, i)) for i, n in enumerate(lengths)]
+    queries = [None] * Q
+    for i, n in enumerate(lengths):
+        sel = np.nonzero(db_of == i)[0]
+        qs = random_walk(len(sel), n, rng(config_id, ROLE_QUERY, 1, i))
+        for j, q in enumerate(sel):
+            queries[q] = qs[j]
+    return dbs, queries, db_of, w
+
+
+def make_serving_workload(rate_qps: float, count: int, N_main: int = 1_000_000, N_side: int = 200_000,
+                          n_main: int = 128, n_side: int = 256, side_share: float = 0.2, ks=(1, 5, 10),
+                          f: float = 0.1, config_id: int = 5, with_databases: bool = True):
+    """Request stream for the serving loop: ``count`` Poisson arrivals at ``rate_qps``; each
+    request asks the main database (length n_main) or, with probability side_share, the side
+    database (length n_side), with w = round(f * n) and k drawn uniformly from ``ks``.
+    Returns (dbs, requests) with dbs = [main, side] random-walk databases (None when
+    with_databases is false) and requests a dict of arrays: t (s), db, w, k and the list
+    ``y`` of query series."""
+    r = rng(config_id, ROLE_ARRIVAL, int(rate_qps))
+    t = poisson_arrivals(rate_qps, count, r)
+    db = (r.random(count) < side_share).astype(np.int32)
+    k = np.asarray(ks, dtype=np.int32)[r.integers(0, len(ks), count)]
+    lengths = (n_main, n_side)
+    w = np.array([band_from_fraction(lengths[b], f) for b in db], dtype=np.int32)
+    yq = random_walk(count, n_side, rng(config_id, ROLE_QUERY, int(rate_qps)))
+    y = [yq[i, :lengths[b]] for i, b in enumerate(db)]
+    dbs = None
+    if with_databases:
+        dbs = [random_walk(N_main, n_main, rng(config_id, ROLE_DB, 0)),
+               random_walk(N_side, n_side, rng(config_id, ROLE_DB, 1))]
+    return dbs, dict(t=t, db=db, w=w, k=k, y=y)

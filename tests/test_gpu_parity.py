@@ -132,7 +132,8 @@ def test_lb_improved(L, ctx, N, n, w, p):
 # ------------------------------------------------------------------ DTW
 @pytest.mark.parametrize("N,n,w", [(70, 1, 0), (70, 2, 1), (130, 64, 0), (130, 128, 13), (65, 256, 26),
                                    (33, 512, 51), (20, 300, 63), (10, 200, 64), (8, 512, 102), (4, 97, 500),
-                                   (3, 1024, 205), (67, 77, 2), (45, 33, 7), (66, 4096, 31), (5, 40, 40)])
+                                   (3, 1024, 205), (67, 77, 2), (45, 33, 7), (66, 4096, 31), (5, 40, 40),
+                                   (130, 300, 80), (70, 129, 128), (65, 66, 65)])
 @pytest.mark.parametrize("p", [1, 2])
 @pytest.mark.parametrize("group", [0, 1])
 def test_dtw_band(L, ctx, N, n, w, p, group):
