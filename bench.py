@@ -144,6 +144,83 @@ def cpu_baseline(X, Ys, w, p, gpu_idx, budget_s=12.0):
                 seconds=total, index_agreement=agree)
 
 
+def ragged_bench(L, ctx, steps, warmup):
+    """Uneven batch: 4,096 random-walk queries, lengths uniform over {64,...,1024}, w = round(f n)
+    with f uniform over {0.05, 0.1, 0.2}, one 20,000-series database per length, p = 1, 1-NN,
+    one lbimp_nn_search_ragged call per step (captured once as a HIP graph, then replayed)."""
+    import torch
+    from paper_0811_3301_amd import gen
+    dbs, qs, db_of, w = gen.make_ragged_workload()
+    handles = [L.Db(ctx, torch.from_numpy(d.astype(np.float32)).cuda()) for d in dbs]
+    off = np.zeros(len(qs) + 1, np.int64)
+    off[1:] = np.cumsum([len(y) for y in qs])
+    packed = torch.from_numpy(np.concatenate(qs).astype(np.float32)).cuda()
+    Q = len(qs)
+    idx = torch.empty((Q, 1), dtype=torch.int64, device="cuda")
+    dist = torch.empty((Q, 1), dtype=torch.float32, device="cuda")
+    out = {}
+    for graph in (1, 0):
+        L.lbimp_ctx_set_option(ctx, "graph", graph)
+        call = lambda: L.lbimp_nn_search_ragged(ctx, handles, packed, off, db_of, w, 1, 1, "improved", idx=idx,
+                                                dist=dist, stats=False)
+        for _ in range(warmup):
+            call()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / steps * 1e3
+        out["graph" if graph else "eager"] = dict(ms_per_step=ms, qps=Q / ms * 1e3)
+    L.lbimp_ctx_set_option(ctx, "graph", 1)
+    _, _, st = L.lbimp_nn_search_ragged(ctx, handles, packed, off, db_of, w, 1, 1, "improved")
+    torch.cuda.synchronize()
+    for h in handles:
+        h.close()
+    return dict(workload="uneven batch: 4096 random-walk queries, n in {64,128,256,512,1024}, w = round(f n), "
+                         "f in {0.05,0.1,0.2}, 20000-series database per length, p=1, 1-NN",
+                queries=Q, groups=len(set(zip(db_of.tolist(), w.tolist()))), **out,
+                dtw_fraction=float(st[:, 4].sum() / st[:, 0].sum()))
+
+
+def serving_bench(L, rates, seconds, max_batch=512, slots=4, budget=16 << 30):
+    """Serving: Poisson arrivals over a resident 1,000,000 x 128 random-walk database (512 MB)
+    and a 200,000 x 256 side database (20% of requests), w = round(0.1 n), k uniform over
+    {1, 5, 10}; continuous batching on `slots` in-flight batches under a device-memory budget."""
+    import torch
+    from paper_0811_3301_amd import gen
+    from paper_0811_3301_amd.serve import GpuExecutor, Request, serve
+    dbs64, _ = gen.make_serving_workload(1.0, 1, with_databases=True)
+    ctx = L.Ctx(0)
+    handles = [L.Db(ctx, torch.from_numpy(d.astype(np.float32)).cuda()) for d in dbs64]
+    del dbs64
+    torch.cuda.synchronize()
+    ex = GpuExecutor(handles, slots=slots, max_batch=max_batch, kmax=10)
+    runs = []
+    try:
+        for i, rate in enumerate([rates[-1]] + list(rates)):  # the first run warms the workspaces up
+            count = max(200, min(int(rate * seconds), 40_000))
+            _, req = gen.make_serving_workload(rate, count, with_databases=False)
+            reqs = [Request(rid=j, t_arrive=float(req["t"][j]), db=int(req["db"][j]),
+                            y=req["y"][j].astype(np.float32), w=int(req["w"][j]), k=int(req["k"][j]))
+                    for j in range(count)]
+            _, summ = serve(reqs, ex, budget_bytes=budget, max_batch=max_batch)
+            if i > 0:
+                summ["offered_rate"] = rate
+                runs.append(summ)
+                log(f"serving at {rate} q/s: p50 {summ['p50_ms']:.3f} ms, p99 {summ['p99_ms']:.3f} ms, "
+                    f"{summ['qps']:.0f} q/s")
+    finally:
+        ex.close()
+        for h in handles:
+            h.close()
+        ctx.close()
+    return dict(workload="serving: Poisson arrivals, 80% n=128 over a resident 1,000,000-series database "
+                         "(512 MB), 20% n=256 over a 200,000-series database, w=round(0.1 n), k in {1,5,10}, "
+                         "two-pass search", slots=slots, max_batch=max_batch, memory_budget_bytes=budget,
+                runs=runs)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +228,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--quick", action="store_true", help="two-pass mode only (for profiling runs)")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the uneven-batch measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
     args = ap.parse_args()
@@ -223,6 +302,16 @@ def main():
         log("single-query LB_Keogh sweep over a 512 MB database")
         lbg = single_query_lb_gbps(L, ctx)
 
+    ragged = None
+    if not (args.quick or args.no_ragged):
+        log("uneven batch (4096 queries of mixed lengths and bands)")
+        ragged = ragged_bench(L, ctx, max(3, args.steps // 4), 2)
+
+    serving = None
+    if not (args.quick or args.no_serving):
+        log("serving loop")
+        serving = serving_bench(L, rates=(1_000, 10_000, 50_000), seconds=0.5)
+
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline")
@@ -255,6 +344,8 @@ def main():
         "stage_ms_p1": stages,
         "lb_single_query_hbm": lbg,
         "batch_latency_ms": dict(p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99))),
+        "ragged": ragged,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     db.close()

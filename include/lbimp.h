@@ -162,6 +162,19 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
                            const int64_t *offsets, const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p,
                            int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
 
+/* Device workspace (bytes) that a context allocates to run lbimp_nn_search_ragged on this
+ * batch (same arguments; query lengths are taken from the databases), written to *bytes.
+ * After the call the context holds at most the larger of its previous workspace and this
+ * size.  A serving loop uses it to admit batches against a device-memory budget before
+ * launching them. */
+int lbimp_nn_search_ragged_workspace(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb,
+                                     const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p, int32_t k,
+                                     int32_t mode, uint64_t *bytes);
+
+/* Device workspace currently held by the context (it grows on demand and is freed with the
+ * context), written to *bytes. */
+int lbimp_ctx_workspace_bytes(lbimp_ctx *ctx, uint64_t *bytes);
+
 #ifdef __cplusplus
 }
 #endif

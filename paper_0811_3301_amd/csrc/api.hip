@@ -97,6 +97,9 @@ struct lbimp_db {
 
 static int persistent_grid(const lbimp_ctx *ctx) { return std::max(1, ctx->num_cu); }  // CUs; kernels size by occupancy
 
+// Workspace allocated for a request of `bytes` (headroom so that slightly larger calls reuse it).
+static size_t reserve_size(size_t bytes) { return align_up(bytes + bytes / 8, 1 << 20); }
+
 static int reserve(lbimp_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->ws_cap) return LBIMP_OK;
     HIPTRY(hipStreamSynchronize(ctx->stream));
@@ -104,7 +107,7 @@ static int reserve(lbimp_ctx *ctx, size_t bytes) {
     if (ctx->ws) HIPTRY(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_cap = 0;
-    size_t cap = align_up(bytes + bytes / 8, 1 << 20);
+    size_t cap = reserve_size(bytes);
     if (hipMalloc(&ctx->ws, cap) != hipSuccess) {
         (void)hipGetLastError();
         ctx->ws = nullptr;
@@ -347,6 +350,71 @@ static int ensure_pool(lbimp_ctx *ctx) {
     HIPTRY(hipEventCreateWithFlags(&ctx->enter_ev, hipEventDisableTiming));
     HIPTRY(hipEventCreateWithFlags(&ctx->exit_ev, hipEventDisableTiming));
     HIPTRY(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
+    return LBIMP_OK;
+}
+
+// Grouping and workspace layout of a ragged batch: queries sharing a database and an
+// effective band form one homogeneous search.  offsets may be null (lengths unchecked).
+struct RaggedPlan {
+    std::map<std::pair<int, int>, std::vector<int64_t>> groups;
+    std::vector<SearchSpec> specs;
+    std::vector<SearchDims> dims;
+    std::vector<SearchBufs> bufs;
+    std::vector<float *> qbuf;
+    std::vector<int64_t *> qmap, qsrc;
+    size_t meta_elems = 0;
+    int64_t *meta = nullptr;
+
+    // workspace: [metadata: per group query ids, then source offsets][per group: queries + search]
+    void carve(Carver &c) {
+        meta = c.take<int64_t>(meta_elems);
+        size_t o = 0;
+        for (size_t g = 0; g < specs.size(); ++g) {
+            qmap[g] = meta ? meta + o : nullptr;
+            qsrc[g] = meta ? meta + o + specs[g].Q : nullptr;
+            o += 2 * (size_t)specs[g].Q;
+        }
+        for (size_t g = 0; g < specs.size(); ++g) {
+            qbuf[g] = c.take<float>((size_t)specs[g].Q * dims[g].n);
+            layout(c, dims[g], bufs[g]);
+        }
+    }
+};
+
+static int plan_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, const int64_t *offsets,
+                       const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p, int32_t k, int32_t mode,
+                       int64_t *idx, float *dist, RaggedPlan &plan) {
+    if (!dbs || ndb < 1 || !db_of || !w) return fail(LBIMP_E_INVALID, "null pointer or no database");
+    for (int i = 0; i < ndb; ++i) {
+        if (!dbs[i]) return fail(LBIMP_E_INVALID, "null database %d", i);
+        if (dbs[i]->device != ctx->device) return fail(LBIMP_E_INVALID, "database %d lives on another device", i);
+    }
+    for (int64_t q = 0; q < Q; ++q) {
+        const int b = db_of[q];
+        if (b < 0 || b >= ndb) return fail(LBIMP_E_INVALID, "query %lld: database %d of %d", (long long)q, b, ndb);
+        if (offsets) {
+            const int64_t len = offsets[q + 1] - offsets[q];
+            if (offsets[q] < 0 || len != dbs[b]->n)
+                return fail(LBIMP_E_INVALID, "query %lld: length %lld, database length %d", (long long)q,
+                            (long long)len, dbs[b]->n);
+        }
+        if (int r = check_search(1, dbs[b]->n, w[q], p, k, mode)) return r;
+        plan.groups[{b, band_of(dbs[b]->n, w[q])}].push_back(q);
+    }
+    const size_t G = plan.groups.size();
+    plan.dims.resize(G);
+    plan.bufs.resize(G);
+    plan.qbuf.resize(G);
+    plan.qmap.resize(G);
+    plan.qsrc.resize(G);
+    plan.specs.reserve(G);
+    for (auto &kv : plan.groups) {
+        const int64_t Qg = (int64_t)kv.second.size();
+        plan.specs.push_back(SearchSpec{dbs[kv.first.first], nullptr, Qg, kv.first.second, p, k, mode, idx, dist,
+                                        nullptr, ctx_knobs(ctx)});
+        if (int r = dims_of(plan.specs.back(), ctx->num_cu, plan.dims[plan.specs.size() - 1])) return r;
+        plan.meta_elems += 2 * (size_t)Qg;
+    }
     return LBIMP_OK;
 }
 
@@ -650,61 +718,26 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     if (int r = check_ctx(ctx)) return r;
     if (Q < 0) return fail(LBIMP_E_INVALID, "negative query count");
     if (Q == 0) return LBIMP_OK;
-    if (!dbs || ndb < 1 || !queries || !offsets || !db_of || !w || !idx || !dist)
-        return fail(LBIMP_E_INVALID, "null pointer or no database");
-    for (int i = 0; i < ndb; ++i) {
-        if (!dbs[i]) return fail(LBIMP_E_INVALID, "null database %d", i);
-        if (dbs[i]->device != ctx->device) return fail(LBIMP_E_INVALID, "database %d lives on another device", i);
-    }
-    // group the queries by (database, effective band); every group is one homogeneous search
-    std::map<std::pair<int, int>, std::vector<int64_t>> groups;
-    for (int64_t q = 0; q < Q; ++q) {
-        const int b = db_of[q];
-        if (b < 0 || b >= ndb) return fail(LBIMP_E_INVALID, "query %lld: database %d of %d", (long long)q, b, ndb);
-        const int64_t len = offsets[q + 1] - offsets[q];
-        if (offsets[q] < 0 || len != dbs[b]->n)
-            return fail(LBIMP_E_INVALID, "query %lld: length %lld, database length %d", (long long)q, (long long)len,
-                        dbs[b]->n);
-        if (int r = check_search(1, dbs[b]->n, w[q], p, k, mode)) return r;
-        groups[{b, band_of(dbs[b]->n, w[q])}].push_back(q);
-    }
-    const int G = (int)groups.size();
-    std::vector<SearchSpec> specs;
-    std::vector<SearchDims> dims(G);
-    std::vector<SearchBufs> bufs(G);
-    std::vector<float *> qbuf(G);
-    std::vector<int64_t *> qmap(G), qsrc(G);
-    specs.reserve(G);
-    for (auto &kv : groups) {
-        const int64_t Qg = (int64_t)kv.second.size();
-        specs.push_back(SearchSpec{dbs[kv.first.first], nullptr, Qg, kv.first.second, p, k, mode, idx, dist, nullptr,
-                                   ctx_knobs(ctx)});
-        if (int r = dims_of(specs.back(), ctx->num_cu, dims[specs.size() - 1])) return r;
-    }
-    // workspace: [metadata: per group query ids and source offsets][per group: gathered queries + search]
-    size_t meta_elems = 0;
-    for (int g = 0; g < G; ++g) meta_elems += 2 * (size_t)specs[g].Q;
-    int64_t *meta = nullptr;
-    auto carve = [&](Carver &c) {
-        meta = c.take<int64_t>(meta_elems);  // per group: query ids, then source offsets, packed
-        size_t o = 0;
-        for (int g = 0; g < G; ++g) {
-            qmap[g] = meta ? meta + o : nullptr;
-            qsrc[g] = meta ? meta + o + specs[g].Q : nullptr;
-            o += 2 * (size_t)specs[g].Q;
-        }
-        for (int g = 0; g < G; ++g) {
-            qbuf[g] = c.take<float>((size_t)specs[g].Q * dims[g].n);
-            layout(c, dims[g], bufs[g]);
-        }
-    };
+    if (!queries || !offsets || !idx || !dist) return fail(LBIMP_E_INVALID, "null pointer");
+    RaggedPlan plan;
+    if (int r = plan_ragged(ctx, dbs, ndb, offsets, db_of, w, Q, p, k, mode, idx, dist, plan)) return r;
+    auto &groups = plan.groups;
+    auto &specs = plan.specs;
+    auto &dims = plan.dims;
+    auto &bufs = plan.bufs;
+    auto &qbuf = plan.qbuf;
+    auto &qmap = plan.qmap;
+    auto &qsrc = plan.qsrc;
+    const int G = (int)specs.size();
+    const size_t meta_elems = plan.meta_elems;
     {
         Carver cv{nullptr};
-        carve(cv);
+        plan.carve(cv);
         if (int r = reserve(ctx, cv.off)) return r;
         Carver c2{static_cast<char *>(ctx->ws)};
-        carve(c2);
+        plan.carve(c2);
     }
+    int64_t *meta = plan.meta;
     // upload the metadata through a pinned staging buffer (outside any captured graph)
     if (int r = ensure_pool(ctx)) return r;
     if (int r = reserve_pinned(ctx, meta_elems * sizeof(int64_t))) return r;
@@ -795,6 +828,28 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
             fill_stats(dims[g], specs[g].Q, h.data(), ids.data(), stats);
         }
     }
+    return LBIMP_OK;
+}
+
+int lbimp_nn_search_ragged_workspace(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb,
+                                     const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p, int32_t k,
+                                     int32_t mode, uint64_t *bytes) {
+    if (int r = check_ctx(ctx)) return r;
+    if (!bytes) return fail(LBIMP_E_INVALID, "null output pointer");
+    *bytes = 0;
+    if (Q < 0) return fail(LBIMP_E_INVALID, "negative query count");
+    if (Q == 0) return LBIMP_OK;
+    RaggedPlan plan;
+    if (int r = plan_ragged(ctx, dbs, ndb, nullptr, db_of, w, Q, p, k, mode, nullptr, nullptr, plan)) return r;
+    Carver cv{nullptr};
+    plan.carve(cv);
+    *bytes = reserve_size(cv.off);
+    return LBIMP_OK;
+}
+
+int lbimp_ctx_workspace_bytes(lbimp_ctx *ctx, uint64_t *bytes) {
+    if (!ctx || !bytes) return fail(LBIMP_E_INVALID, "null argument");
+    *bytes = ctx->ws_cap;
     return LBIMP_OK;
 }
 

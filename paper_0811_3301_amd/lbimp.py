@@ -56,6 +56,10 @@ SIGNATURES = {
     "lbimp_nn_search_ragged": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i32, _vp, ctypes.POINTER(_i64),
                                               ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i64, _i32, _i32, _i32,
                                               _vp, _vp, ctypes.POINTER(LbimpStats)]),
+    "lbimp_nn_search_ragged_workspace": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i32),
+                                                        ctypes.POINTER(_i32), _i64, _i32, _i32, _i32,
+                                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "lbimp_ctx_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 _lib = None
@@ -272,3 +276,24 @@ def lbimp_nn_search_ragged(ctx: Ctx, dbs, queries: torch.Tensor, offsets, db_of,
         wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p, k, mode, _dev(idx, "idx", torch.int64), _dev(dist, "dist"),
         st), "lbimp_nn_search_ragged")
     return idx, dist, (_stats_array(st, Q) if stats else None)
+
+
+def lbimp_nn_search_ragged_workspace(ctx: Ctx, dbs, db_of, w, p: int, k: int = 1, mode="improved") -> int:
+    """Device workspace (bytes) lbimp_nn_search_ragged needs for this batch on `ctx`."""
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    dof = np.ascontiguousarray(db_of, dtype=np.int32)
+    Q = dof.shape[0]
+    wq = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.int32), (Q,)))
+    handles = (_vp * max(len(dbs), 1))(*[d.h for d in dbs])
+    out = ctypes.c_uint64(0)
+    _check(_lib.lbimp_nn_search_ragged_workspace(ctx.h, handles, len(dbs), dof.ctypes.data_as(ctypes.POINTER(_i32)),
+                                                 wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p, k, mode,
+                                                 ctypes.byref(out)), "lbimp_nn_search_ragged_workspace")
+    return int(out.value)
+
+
+def lbimp_ctx_workspace_bytes(ctx: Ctx) -> int:
+    out = ctypes.c_uint64(0)
+    _check(_lib.lbimp_ctx_workspace_bytes(ctx.h, ctypes.byref(out)), "lbimp_ctx_workspace_bytes")
+    return int(out.value)
