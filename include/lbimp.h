@@ -89,7 +89,11 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *                   5 = 8x2, 1 = 16x2);
  *   "graph"         0/1 (default 1): lbimp_nn_search_ragged captures its launches once as a
  *                   HIP graph and replays it while the call's pointers and grouping are
- *                   unchanged (0: launches them directly).
+ *                   unchanged (0: launches them directly);
+ *   "ragged_streams" 0..4 (default 4): streams over which lbimp_nn_search_ragged spreads its
+ *                   groups; 0 or 1 runs them one after another on the context's stream (with
+ *                   "graph" 0 no other stream is touched, which suits callers that already
+ *                   overlap several contexts).
  * Returns LBIMP_E_INVALID for an unknown name or an out-of-range value. */
 int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
 

@@ -60,6 +60,14 @@ struct Carver {
     }
 };
 
+// Pinned host buffer for an upload; `ev` marks the end of the last copy that read it.
+struct PinnedChunk {
+    void *ptr = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+};
+constexpr size_t kPinnedRing = 8;
+
 }  // namespace
 
 struct lbimp_ctx {
@@ -75,15 +83,15 @@ struct lbimp_ctx {
     bool dtw_low_latency = false;  // option "dtw_group_per_pair" (lbimp_dtw_band only)
     int sweep_shape = 0;           // option "sweep_shape"
     bool use_graph = true;         // option "graph" (lbimp_nn_search_ragged)
+    int ragged_streams = kPoolStreams;  // option "ragged_streams"
     // ragged batches: stream pool, captured graph, pinned staging of the grouping metadata
     hipStream_t graph_stream = nullptr;
     hipStream_t pool[kPoolStreams] = {};
     hipEvent_t join_ev[kPoolStreams] = {};
-    hipEvent_t fork_ev = nullptr, enter_ev = nullptr, exit_ev = nullptr, pinned_ev = nullptr;
+    hipEvent_t fork_ev = nullptr, enter_ev = nullptr, exit_ev = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_sig = 0;
-    void *pinned = nullptr;
-    size_t pinned_cap = 0;
+    std::vector<PinnedChunk> pinned;  // ring of staging buffers, each reusable once its upload ran
     hipEvent_t ev[kStages + 1] = {};
 };
 
@@ -320,22 +328,45 @@ static int check_search(int64_t Q, int32_t n, int32_t w, int32_t p, int32_t k, i
     return LBIMP_OK;
 }
 
-static int reserve_pinned(lbimp_ctx *ctx, size_t bytes) {
-    if (bytes <= ctx->pinned_cap) {
-        if (ctx->pinned_ev) HIPTRY(hipEventSynchronize(ctx->pinned_ev));  // the last upload has read it
-        return LBIMP_OK;
+// A staging buffer of at least `bytes` whose previous upload has completed: the host waits
+// only when every buffer of the ring is still being read.
+static int acquire_pinned(lbimp_ctx *ctx, size_t bytes, PinnedChunk **out) {
+    for (auto &c : ctx->pinned) {
+        if (c.cap < bytes) continue;
+        const hipError_t e = hipEventQuery(c.ev);
+        if (e == hipSuccess) {
+            *out = &c;
+            return LBIMP_OK;
+        }
+        if (e != hipErrorNotReady) return fail(LBIMP_E_DEVICE, "hipEventQuery: %s", hipGetErrorString(e));
     }
-    if (ctx->pinned_ev) HIPTRY(hipEventSynchronize(ctx->pinned_ev));
-    if (ctx->pinned) HIPTRY(hipHostFree(ctx->pinned));
-    ctx->pinned = nullptr;
-    ctx->pinned_cap = 0;
-    size_t cap = align_up(bytes + bytes / 4, 1 << 16);
-    if (hipHostMalloc(&ctx->pinned, cap, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        ctx->pinned = nullptr;
-        return fail(LBIMP_E_NOMEM, "pinned staging allocation of %zu bytes failed", cap);
+    PinnedChunk *slot = nullptr;
+    if (ctx->pinned.size() < kPinnedRing) {
+        ctx->pinned.emplace_back();
+        slot = &ctx->pinned.back();
+        HIPTRY(hipEventCreateWithFlags(&slot->ev, hipEventDisableTiming));
+    } else {
+        slot = &ctx->pinned[0];  // the ring is full: reuse the first buffer once its copy has run
+        for (auto &c : ctx->pinned)
+            if (c.cap >= bytes) {
+                slot = &c;
+                break;
+            }
+        HIPTRY(hipEventSynchronize(slot->ev));
     }
-    ctx->pinned_cap = cap;
+    if (slot->cap < bytes) {
+        if (slot->ptr) HIPTRY(hipHostFree(slot->ptr));
+        slot->ptr = nullptr;
+        slot->cap = 0;
+        const size_t cap = align_up(std::max<size_t>(bytes + bytes / 4, 1 << 16), 1 << 16);
+        if (hipHostMalloc(&slot->ptr, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            slot->ptr = nullptr;
+            return fail(LBIMP_E_NOMEM, "pinned staging allocation of %zu bytes failed", cap);
+        }
+        slot->cap = cap;
+    }
+    *out = slot;
     return LBIMP_OK;
 }
 
@@ -349,7 +380,6 @@ static int ensure_pool(lbimp_ctx *ctx) {
     HIPTRY(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
     HIPTRY(hipEventCreateWithFlags(&ctx->enter_ev, hipEventDisableTiming));
     HIPTRY(hipEventCreateWithFlags(&ctx->exit_ev, hipEventDisableTiming));
-    HIPTRY(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
     return LBIMP_OK;
 }
 
@@ -457,10 +487,13 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx) {
         if (ctx->pool[i]) (void)hipStreamDestroy(ctx->pool[i]);
         if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
     }
-    for (hipEvent_t e : {ctx->fork_ev, ctx->enter_ev, ctx->exit_ev, ctx->pinned_ev})
+    for (hipEvent_t e : {ctx->fork_ev, ctx->enter_ev, ctx->exit_ev})
         if (e) (void)hipEventDestroy(e);
     if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (auto &c : ctx->pinned) {
+        if (c.ev) (void)hipEventSynchronize(c.ev), (void)hipEventDestroy(c.ev);
+        if (c.ptr) (void)hipHostFree(c.ptr);
+    }
     if (ctx->ws) (void)hipFree(ctx->ws);
     delete ctx;
 }
@@ -485,6 +518,10 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         ctx->dtw_low_latency = value != 0;
     } else if (!strcmp(name, "graph")) {
         ctx->use_graph = value != 0;
+    } else if (!strcmp(name, "ragged_streams")) {
+        if (value < 0 || value > kPoolStreams)
+            return fail(LBIMP_E_INVALID, "ragged_streams must be in [0, %d]", kPoolStreams);
+        ctx->ragged_streams = (int)value;
     } else if (!strcmp(name, "sweep_shape")) {
         if (value < 0 || value > 5) return fail(LBIMP_E_INVALID, "sweep_shape must be in [0, 5]");
         ctx->sweep_shape = (int)value;
@@ -739,18 +776,23 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     }
     int64_t *meta = plan.meta;
     // upload the metadata through a pinned staging buffer (outside any captured graph)
-    if (int r = ensure_pool(ctx)) return r;
-    if (int r = reserve_pinned(ctx, meta_elems * sizeof(int64_t))) return r;
     {
-        int64_t *h = static_cast<int64_t *>(ctx->pinned);
+        PinnedChunk *pc = nullptr;
+        if (int r = acquire_pinned(ctx, meta_elems * sizeof(int64_t), &pc)) return r;
+        int64_t *h = static_cast<int64_t *>(pc->ptr);
         size_t o = 0;
         for (auto &kv : groups) {
             for (int64_t q : kv.second) h[o++] = q;
             for (int64_t q : kv.second) h[o++] = offsets[q];
         }
         HIPTRY(hipMemcpyAsync(meta, h, meta_elems * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
-        HIPTRY(hipEventRecord(ctx->pinned_ev, ctx->stream));
+        HIPTRY(hipEventRecord(pc->ev, ctx->stream));
     }
+    // groups run concurrently on `width` pool streams (forked from and joined back to the
+    // launching stream), or one after another on the launching stream when width <= 1
+    const int width = std::min(ctx->ragged_streams, G);
+    if (ctx->use_graph || width > 1)
+        if (int r = ensure_pool(ctx)) return r;
     for (int g = 0; g < G; ++g) {
         specs[g].queries = qbuf[g];
         specs[g].qmap = qmap[g];
@@ -758,16 +800,20 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     // the groups run concurrently on the context's stream pool, captured once as a graph and
     // replayed while the call's signature (pointers, shapes, grouping, workspace) is unchanged
     auto enqueue_all = [&](hipStream_t main) -> int {
-        HIPTRY(hipEventRecord(ctx->fork_ev, main));
-        for (int i = 0; i < kPoolStreams; ++i) HIPTRY(hipStreamWaitEvent(ctx->pool[i], ctx->fork_ev, 0));
+        if (width > 1) {
+            HIPTRY(hipEventRecord(ctx->fork_ev, main));
+            for (int i = 0; i < width; ++i) HIPTRY(hipStreamWaitEvent(ctx->pool[i], ctx->fork_ev, 0));
+        }
         for (int g = 0; g < G; ++g) {
-            hipStream_t sg = ctx->pool[g % kPoolStreams];
+            hipStream_t sg = width > 1 ? ctx->pool[g % width] : main;
             HIPTRY(launch_gather_rows(queries, qsrc[g], dims[g].n, specs[g].Q, qbuf[g], sg));
             if (int r = enqueue_search(ctx, specs[g], dims[g], bufs[g], sg, false)) return r;
         }
-        for (int i = 0; i < kPoolStreams; ++i) {
-            HIPTRY(hipEventRecord(ctx->join_ev[i], ctx->pool[i]));
-            HIPTRY(hipStreamWaitEvent(main, ctx->join_ev[i], 0));
+        if (width > 1) {
+            for (int i = 0; i < width; ++i) {
+                HIPTRY(hipEventRecord(ctx->join_ev[i], ctx->pool[i]));
+                HIPTRY(hipStreamWaitEvent(main, ctx->join_ev[i], 0));
+            }
         }
         return LBIMP_OK;
     };
@@ -779,6 +825,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     mix((uint64_t)(uintptr_t)dist);
     mix((uint64_t)Q);
     mix((uint64_t)(p * 131 + k * 7 + mode));
+    mix((uint64_t)width);
     for (int g = 0; g < G; ++g) {
         const lbimp_db *db = specs[g].db;  // a database freed and recreated may reuse an address
         mix((uint64_t)(uintptr_t)db);
@@ -790,35 +837,39 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         mix((uint64_t)specs[g].w);
         mix((uint64_t)(specs[g].kn.seeds * 1000 + specs[g].kn.sweep_shape * 10 + specs[g].kn.lbi_pipeline));
     }
-    HIPTRY(hipEventRecord(ctx->enter_ev, ctx->stream));
-    HIPTRY(hipStreamWaitEvent(ctx->graph_stream, ctx->enter_ev, 0));
-    if (ctx->use_graph) {
-        if (!ctx->graph_exec || ctx->graph_sig != sig) {
-            if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
-            ctx->graph_exec = nullptr;
-            hipGraph_t graph = nullptr;
-            HIPTRY(hipStreamBeginCapture(ctx->graph_stream, hipStreamCaptureModeRelaxed));
-            int r = enqueue_all(ctx->graph_stream);
-            hipError_t e = hipStreamEndCapture(ctx->graph_stream, &graph);
-            if (r) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return r;
-            }
-            if (e != hipSuccess) return fail(LBIMP_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) {
-                ctx->graph_exec = nullptr;
-                return fail(LBIMP_E_DEVICE, "graph instantiation: %s", hipGetErrorString(e));
-            }
-            ctx->graph_sig = sig;
-        }
-        HIPTRY(hipGraphLaunch(ctx->graph_exec, ctx->graph_stream));
+    if (!ctx->use_graph && width <= 1) {
+        if (int r = enqueue_all(ctx->stream)) return r;
     } else {
-        if (int r = enqueue_all(ctx->graph_stream)) return r;
+        HIPTRY(hipEventRecord(ctx->enter_ev, ctx->stream));
+        HIPTRY(hipStreamWaitEvent(ctx->graph_stream, ctx->enter_ev, 0));
+        if (ctx->use_graph) {
+            if (!ctx->graph_exec || ctx->graph_sig != sig) {
+                if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+                ctx->graph_exec = nullptr;
+                hipGraph_t graph = nullptr;
+                HIPTRY(hipStreamBeginCapture(ctx->graph_stream, hipStreamCaptureModeRelaxed));
+                int r = enqueue_all(ctx->graph_stream);
+                hipError_t e = hipStreamEndCapture(ctx->graph_stream, &graph);
+                if (r) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return r;
+                }
+                if (e != hipSuccess) return fail(LBIMP_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+                e = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) {
+                    ctx->graph_exec = nullptr;
+                    return fail(LBIMP_E_DEVICE, "graph instantiation: %s", hipGetErrorString(e));
+                }
+                ctx->graph_sig = sig;
+            }
+            HIPTRY(hipGraphLaunch(ctx->graph_exec, ctx->graph_stream));
+        } else {
+            if (int r = enqueue_all(ctx->graph_stream)) return r;
+        }
+        HIPTRY(hipEventRecord(ctx->exit_ev, ctx->graph_stream));
+        HIPTRY(hipStreamWaitEvent(ctx->stream, ctx->exit_ev, 0));
     }
-    HIPTRY(hipEventRecord(ctx->exit_ev, ctx->graph_stream));
-    HIPTRY(hipStreamWaitEvent(ctx->stream, ctx->exit_ev, 0));
     if (stats) {
         HIPTRY(hipStreamSynchronize(ctx->stream));
         for (int g = 0; g < G; ++g) {

@@ -141,8 +141,10 @@ class GpuExecutor:
             stream = torch.cuda.Stream()
             with torch.cuda.stream(stream):
                 ctx = L.Ctx(0)
-            # batches change shape from one launch to the next: launch directly, no graph capture
+            # batches change shape from one launch to the next: launch directly, no graph capture,
+            # and keep each batch on its slot's stream (the slots already overlap each other)
             L.lbimp_ctx_set_option(ctx, "graph", 0)
+            L.lbimp_ctx_set_option(ctx, "ragged_streams", 0)
             elems = max_batch * max_len
             self.slots.append(_Slot(
                 ctx=ctx, stream=stream,

@@ -69,16 +69,18 @@ def _alone(L, ctx, handles, db_of, w, Ys, p, k, mode, n_of):
 
 @pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
 @pytest.mark.parametrize("p,k", [(1, 1), (2, 5)])
-@pytest.mark.parametrize("graph", [0, 1])
-def test_ragged_matches_oracle_and_alone(L, ctx, dbs, mode, p, k, graph):
-    _say(f"ragged mix mode={mode} p={p} k={k} graph={graph}")
+@pytest.mark.parametrize("graph,streams", [(0, 4), (1, 4), (0, 0), (1, 1)])
+def test_ragged_matches_oracle_and_alone(L, ctx, dbs, mode, p, k, graph, streams):
+    _say(f"ragged mix mode={mode} p={p} k={k} graph={graph} streams={streams}")
     Xs, handles = dbs
     db_of, w, Ys, offsets, packed = _mix(1 + p + 3 * k, 37, LENGTHS, BANDS)
     L.lbimp_ctx_set_option(ctx, "graph", graph)
+    L.lbimp_ctx_set_option(ctx, "ragged_streams", streams)
     try:
         idx, dist, st = L.lbimp_nn_search_ragged(ctx, handles, to_dev(packed), offsets, db_of, w, p, k, mode)
     finally:
         L.lbimp_ctx_set_option(ctx, "graph", 1)
+        L.lbimp_ctx_set_option(ctx, "ragged_streams", 4)
     idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
     _check_against_oracle(Xs, db_of, w, Ys, p, k, idx, dist, f"ragged {mode}")
     ai, ad, ast = _alone(L, ctx, handles, db_of, w, Ys, p, k, mode, LENGTHS)
