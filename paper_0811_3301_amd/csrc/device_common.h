@@ -182,6 +182,10 @@ struct LbiArgs {
     bool pipeline;  // software-pipelined staging (more registers, fewer exposed load latencies)
 };
 
+// Wave-per-pair LB_Improved for wide bands (n + w <= 2048, 2w + 1 larger than a lane's slice).
+bool lbi_wave_supported(int n, int w);
+hipError_t launch_lbi_wave(int p, int w, int num_cu, const LbiArgs &a, hipStream_t s);
+
 hipError_t launch_lbi_reg_p1(int w, int num_cu, const LbiArgs &a, hipStream_t s);
 hipError_t launch_lbi_reg_p2(int w, int num_cu, const LbiArgs &a, hipStream_t s);
 

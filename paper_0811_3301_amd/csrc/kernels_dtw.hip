@@ -7,7 +7,8 @@
 namespace lbimp {
 
 // ------------------------------------------------------------------ LB_Improved (Sec. 8)
-// Lane per (query, candidate) pair, WL pairs per wave, all of one query.  For the candidate
+// Generic fallback for bands neither the register kernel nor the wave kernel takes (series
+// longer than 2048 with w > 52): lane per (query, candidate) pair, WL pairs per wave.  For the candidate
 // x: x' = H(x, y) = med3(x, L, U) (eq. of H), its envelope (U', L') with the same w, and the
 // second term sum_i d(y_i, [L'_i, U'_i])^p.  The envelope of x' is streamed with van Herk /
 // Gil-Werman blocks of K = 2w+1: walking e forward through block B keeps g = running max/min
@@ -15,7 +16,7 @@ namespace lbimp {
 // block B-1 at offset o+1 (or at B's start when o = K-1), whose suffix max/min h was stored
 // by a backward walk over block B-1.  Only h (2(K+1) floats per lane) lives in LDS.
 int lbi_batch(int n, int w) {
-    if (w <= kLbiRegMaxW) return 64;
+    if (w <= kLbiRegMaxW || lbi_wave_supported(n, w)) return 64;
     const size_t K = 2 * (size_t)w + 1;
     const size_t fixed = 3 * 4 * (size_t)n;
     if (fixed >= kLdsBudget) return 0;
@@ -126,8 +127,9 @@ hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, 
                       int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
                       bool pipeline, hipStream_t s) {
-    if (w <= kLbiRegMaxW) {
+    if (w <= kLbiRegMaxW || lbi_wave_supported(n, w)) {
         LbiArgs a{rows, db_bytes, n, qd, pl, S1, ldS, prefix, Q, ctr, thr, list2, ldl2, cnt2, out_root, pipeline};
+        if (w > kLbiRegMaxW) return launch_lbi_wave(p, w, num_cu, a, s);
         return p == 1 ? launch_lbi_reg_p1(w, num_cu, a, s) : launch_lbi_reg_p2(w, num_cu, a, s);
     }
     const int WL = lbi_batch(n, w);
