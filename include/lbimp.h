@@ -90,6 +90,8 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *   "graph"         0/1 (default 1): lbimp_nn_search_ragged captures its launches once as a
  *                   HIP graph and replays it while the call's pointers and grouping are
  *                   unchanged (0: launches them directly);
+ *   "autotune"      0/1 (default 0): lbimp_nn_search and lbimp_nn_search_ragged run
+ *                   lbimp_autotune on every batch shape they meet for the first time;
  *   "ragged_streams" 0..4 (default 4): streams over which lbimp_nn_search_ragged spreads its
  *                   groups; 0 or 1 runs them one after another on the context's stream (with
  *                   "graph" 0 no other stream is touched, which suits callers that already
@@ -165,6 +167,20 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
 int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, const float *queries,
                            const int64_t *offsets, const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p,
                            int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
+
+/* Autotuner.  Runs the search of this batch (arguments as lbimp_nn_search) under candidate
+ * choices that change speed and never results -- the number of seeding DTWs, the LB_Keogh
+ * sweep tiling, a lane or a group of lanes per pair for the seeding and for the survivors'
+ * DTW, pipelined LB_Improved loads -- timing each with HIP events on the context's stream
+ * (one choice at a time from the best so far), and keeps the fastest for every later batch
+ * of the same shape (database size and length, effective band, p, k, mode, and Q rounded up
+ * to a power of two) in lbimp_nn_search and lbimp_nn_search_ragged.  With the context option
+ * "autotune" set, those calls tune a shape they meet for the first time by themselves.
+ * choice: host [LBIMP_TUNE_KNOBS] or NULL, receives {seeds, sweep_shape, lbi_pipeline,
+ * survivors' DTW group-per-pair, seeding DTW lane-per-pair}.  Waits for the stream. */
+#define LBIMP_TUNE_KNOBS 5
+int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
+                   int32_t k, int32_t mode, int32_t *choice);
 
 /* Device workspace (bytes) that a context allocates to run lbimp_nn_search_ragged on this
  * batch (same arguments; query lengths are taken from the databases), written to *bytes.

@@ -6,6 +6,7 @@
 // starts at infinity and shrinks in database order, is replaced by a seeded threshold: the
 // DTW of the candidates with the smallest LB_Keogh, computed first.
 #include <algorithm>
+#include <array>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -13,6 +14,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -68,6 +70,21 @@ struct PinnedChunk {
 };
 constexpr size_t kPinnedRing = 8;
 
+// Batches that share a tuning choice: database shape, band, p, k, mode, Q up to a power of 2.
+struct TuneKey {
+    int64_t N;
+    int n, wb, p, k, mode, qb;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(N, n, wb, p, k, mode, qb) < std::tie(o.N, o.n, o.wb, o.p, o.k, o.mode, o.qb);
+    }
+};
+
+int pow2_at_least(int64_t v) {
+    int b = 1;
+    while (b < v && b < (1 << 30)) b <<= 1;
+    return b;
+}
+
 }  // namespace
 
 struct lbimp_ctx {
@@ -92,6 +109,9 @@ struct lbimp_ctx {
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_sig = 0;
     std::vector<PinnedChunk> pinned;  // ring of staging buffers, each reusable once its upload ran
+    bool autotune = false;            // option "autotune"
+    std::map<TuneKey, std::array<int, 5>> tuned;  // seeds, sweep_shape, lbi_pipeline, dtw_group, seed_lane
+    hipEvent_t tev[2] = {};
     hipEvent_t ev[kStages + 1] = {};
 };
 
@@ -150,10 +170,13 @@ static void stage_mark(lbimp_ctx *ctx, int i) {
 // ------------------------------------------------------------------ one homogeneous search
 namespace {
 
+// Choices that change speed, never results.
 struct Knobs {
-    int seeds;
-    bool lbi_pipeline;
-    int sweep_shape;
+    int seeds;          // seeding DTWs (at least k are used)
+    bool lbi_pipeline;  // pipelined loads in the register LB_Improved kernel
+    int sweep_shape;    // tiling of the LB_Keogh sweep
+    bool dtw_group;     // survivors' DTW with a group of lanes per pair (else a lane per pair)
+    bool seed_lane;     // seeding DTWs with a lane per pair (else a group of lanes per pair)
 };
 
 struct SearchSpec {  // Q queries of one length against one database
@@ -288,10 +311,11 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         stage(3);
         // Seeds: few pairs per query on the critical path, so a group of lanes per pair (low
         // latency); they run to completion, their DTWs finishing together.
-        HIPTRY(launch_items_prefix(nullptr, d.S, Q, dtw_batch(n, wb, true), b.prefix, s));
+        const bool seed_ll = !sp.kn.seed_lane;
+        HIPTRY(launch_items_prefix(nullptr, d.S, Q, dtw_batch(n, wb, seed_ll), b.prefix, s));
         PairList seedl{b.seeds, d.S, nullptr, d.S};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, seedl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, true, b.ring,
+                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, seed_ll, b.ring,
                           d.ring_bytes, s));
         if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, b.thr, s));
         stage(4);
@@ -305,9 +329,10 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
             dl = PairList{b.list2, N, cnt2, 0};
         }
         stage(6);
-        HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, false), b.prefix, s));
+        const bool dtw_ll = sp.kn.dtw_group && wb <= kLaneMaxW;
+        HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, dtw_ll), b.prefix, s));
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, false, b.ring,
+                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, dtw_ll, b.ring,
                           d.ring_bytes, s));
     }
     stage(7);
@@ -319,7 +344,146 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     return LBIMP_OK;
 }
 
-static Knobs ctx_knobs(const lbimp_ctx *ctx) { return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape}; }
+static Knobs ctx_knobs(const lbimp_ctx *ctx) {
+    return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false};
+}
+
+static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int mode) {
+    return TuneKey{db->N, db->n, wb, p, k, mode, pow2_at_least(Q)};
+}
+
+static Knobs knobs_of(const std::array<int, 5> &v) {
+    return Knobs{v[0], v[2] != 0, v[1], v[3] != 0, v[4] != 0};
+}
+
+static std::array<int, 5> knob_values(const Knobs &k) {
+    return {k.seeds, k.sweep_shape, k.lbi_pipeline ? 1 : 0, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0};
+}
+
+// The tuned choice for this batch shape if there is one, else the context's options.
+static Knobs knobs_for(const lbimp_ctx *ctx, const lbimp_db *db, int64_t Q, int wb, int p, int k, int mode) {
+    auto it = ctx->tuned.find(tune_key(db, Q, wb, p, k, mode));
+    return it == ctx->tuned.end() ? ctx_knobs(ctx) : knobs_of(it->second);
+}
+
+static int check_search(int64_t Q, int32_t n, int32_t w, int32_t p, int32_t k, int32_t mode);
+static int acquire_pinned(lbimp_ctx *ctx, size_t bytes, PinnedChunk **out);
+
+// Autotuner: times the whole search of this batch (on the context's stream, HIP events) under
+// candidate choices -- seeds, sweep tiling, lane- or group-per-pair DTW for seeds and for
+// survivors, pipelined LB_Improved loads -- one knob at a time from the current best (a
+// coordinate descent), and records the fastest for the batch's TuneKey.  The queries are
+// either device [Q][n] (`qdev`) or gathered from a packed array by host offsets.  Every
+// candidate computes the same result; only time differs.
+static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, const float *packed,
+                       const int64_t *host_off, int64_t Q, int wb, int p, int k, int mode, Knobs *out) {
+    const int n = db->n;
+    const bool brute = mode == LBIMP_MODE_BRUTE, improved = mode == LBIMP_MODE_IMPROVED;
+    const int seed_opts[] = {8, 16, 32, 64};
+    const int shape_opts[] = {0, 2, 3, 4, 5};
+    // workspace: [queries (gathered) | offsets | idx | dist][search buffers of the largest candidate]
+    size_t search_bytes = 0;
+    for (int sd : seed_opts)
+        for (int sh : shape_opts) {
+            SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr, Knobs{sd, true, sh, false, false}};
+            SearchDims d;
+            if (int r = dims_of(sp, ctx->num_cu, d)) return r;
+            SearchBufs b;
+            Carver cv{nullptr};
+            layout(cv, d, b);
+            search_bytes = std::max(search_bytes, cv.off);
+        }
+    auto carve_tune = [&](Carver &c, float *&qb, int64_t *&ob, int64_t *&ib, float *&db_) {
+        qb = qdev ? nullptr : c.take<float>((size_t)Q * n);
+        ob = qdev ? nullptr : c.take<int64_t>((size_t)Q);
+        ib = c.take<int64_t>((size_t)Q * k);
+        db_ = c.take<float>((size_t)Q * k);
+        c.off = align_up(c.off, 256);
+    };
+    float *qb = nullptr, *dist = nullptr;
+    int64_t *ob = nullptr, *idx = nullptr;
+    size_t head = 0;
+    {
+        Carver cv{nullptr};
+        carve_tune(cv, qb, ob, idx, dist);
+        head = cv.off;
+        if (int r = reserve(ctx, head + search_bytes)) return r;
+        Carver c2{static_cast<char *>(ctx->ws)};
+        carve_tune(c2, qb, ob, idx, dist);
+    }
+    hipStream_t s = ctx->stream;
+    const float *queries = qdev;
+    if (!qdev) {  // gather the batch's queries into the tuning area
+        PinnedChunk *pc = nullptr;
+        if (int r = acquire_pinned(ctx, sizeof(int64_t) * (size_t)Q, &pc)) return r;
+        std::memcpy(pc->ptr, host_off, sizeof(int64_t) * (size_t)Q);
+        HIPTRY(hipMemcpyAsync(ob, pc->ptr, sizeof(int64_t) * (size_t)Q, hipMemcpyHostToDevice, s));
+        HIPTRY(hipEventRecord(pc->ev, s));
+        HIPTRY(launch_gather_rows(packed, ob, n, Q, qb, s));
+        queries = qb;
+    }
+    for (auto &e : ctx->tev)
+        if (!e) HIPTRY(hipEventCreate(&e));
+    auto time_of = [&](const Knobs &kn, float *ms) -> int {
+        SearchSpec sp{db, queries, Q, wb, p, k, mode, idx, dist, nullptr, kn};
+        SearchDims d;
+        if (int r = dims_of(sp, ctx->num_cu, d)) return r;
+        SearchBufs b;
+        Carver c{static_cast<char *>(ctx->ws) + head};
+        layout(c, d, b);
+        if (int r = enqueue_search(ctx, sp, d, b, s, false)) return r;  // warm-up
+        HIPTRY(hipEventRecord(ctx->tev[0], s));
+        for (int rep = 0; rep < 2; ++rep)
+            if (int r = enqueue_search(ctx, sp, d, b, s, false)) return r;
+        HIPTRY(hipEventRecord(ctx->tev[1], s));
+        HIPTRY(hipEventSynchronize(ctx->tev[1]));
+        HIPTRY(hipEventElapsedTime(ms, ctx->tev[0], ctx->tev[1]));
+        return LBIMP_OK;
+    };
+    Knobs best = ctx_knobs(ctx);
+    float best_ms = 0.f;
+    if (int r = time_of(best, &best_ms)) return r;
+    auto consider = [&](Knobs kn) -> int {
+        if (knob_values(kn) == knob_values(best)) return LBIMP_OK;
+        float ms = 0.f;
+        if (int r = time_of(kn, &ms)) return r;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = kn;
+        }
+        return LBIMP_OK;
+    };
+    if (!brute) {
+        const Knobs b0 = best;
+        for (int sd : seed_opts) {
+            Knobs kn = b0;
+            kn.seeds = sd;
+            if (int r = consider(kn)) return r;
+        }
+        const Knobs b1 = best;
+        for (int sh : shape_opts) {
+            Knobs kn = b1;
+            kn.sweep_shape = sh;
+            if (int r = consider(kn)) return r;
+        }
+        Knobs kn = best;
+        kn.seed_lane = !kn.seed_lane;
+        if (int r = consider(kn)) return r;
+    }
+    if (wb <= kLaneMaxW) {
+        Knobs kn = best;
+        kn.dtw_group = !kn.dtw_group;
+        if (int r = consider(kn)) return r;
+    }
+    if (improved && wb <= kLbiRegMaxW) {
+        Knobs kn = best;
+        kn.lbi_pipeline = !kn.lbi_pipeline;
+        if (int r = consider(kn)) return r;
+    }
+    ctx->tuned[tune_key(db, Q, wb, p, k, mode)] = knob_values(best);
+    *out = best;
+    return LBIMP_OK;
+}
 
 static int check_search(int64_t Q, int32_t n, int32_t w, int32_t p, int32_t k, int32_t mode) {
     if (int r = check_shape(Q, n, w, p)) return r;
@@ -440,8 +604,9 @@ static int plan_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, 
     plan.specs.reserve(G);
     for (auto &kv : plan.groups) {
         const int64_t Qg = (int64_t)kv.second.size();
-        plan.specs.push_back(SearchSpec{dbs[kv.first.first], nullptr, Qg, kv.first.second, p, k, mode, idx, dist,
-                                        nullptr, ctx_knobs(ctx)});
+        const lbimp_db *db = dbs[kv.first.first];
+        plan.specs.push_back(SearchSpec{db, nullptr, Qg, kv.first.second, p, k, mode, idx, dist, nullptr,
+                                        knobs_for(ctx, db, Qg, kv.first.second, p, k, mode)});
         if (int r = dims_of(plan.specs.back(), ctx->num_cu, plan.dims[plan.specs.size() - 1])) return r;
         plan.meta_elems += 2 * (size_t)Qg;
     }
@@ -487,7 +652,7 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx) {
         if (ctx->pool[i]) (void)hipStreamDestroy(ctx->pool[i]);
         if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
     }
-    for (hipEvent_t e : {ctx->fork_ev, ctx->enter_ev, ctx->exit_ev})
+    for (hipEvent_t e : {ctx->fork_ev, ctx->enter_ev, ctx->exit_ev, ctx->tev[0], ctx->tev[1]})
         if (e) (void)hipEventDestroy(e);
     if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
     for (auto &c : ctx->pinned) {
@@ -518,6 +683,8 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         ctx->dtw_low_latency = value != 0;
     } else if (!strcmp(name, "graph")) {
         ctx->use_graph = value != 0;
+    } else if (!strcmp(name, "autotune")) {
+        ctx->autotune = value != 0;
     } else if (!strcmp(name, "ragged_streams")) {
         if (value < 0 || value > kPoolStreams)
             return fail(LBIMP_E_INVALID, "ragged_streams must be in [0, %d]", kPoolStreams);
@@ -726,7 +893,12 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     if (int r = check_search(Q, db->n, w, p, k, mode)) return r;
     if (Q == 0) return LBIMP_OK;
     if (!queries || !idx || !dist) return fail(LBIMP_E_INVALID, "null pointer");
-    SearchSpec sp{db, queries, Q, w, p, k, mode, idx, dist, nullptr, ctx_knobs(ctx)};
+    const int wb = band_of(db->n, w);
+    if (ctx->autotune && db->N > 0 && !ctx->tuned.count(tune_key(db, Q, wb, p, k, mode))) {
+        Knobs tuned;
+        if (int r = tune_search(ctx, db, queries, nullptr, nullptr, Q, wb, p, k, mode, &tuned)) return r;
+    }
+    SearchSpec sp{db, queries, Q, w, p, k, mode, idx, dist, nullptr, knobs_for(ctx, db, Q, wb, p, k, mode)};
     SearchDims d;
     if (int r = dims_of(sp, ctx->num_cu, d)) return r;
     SearchBufs bufs;
@@ -758,6 +930,23 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     if (!queries || !offsets || !idx || !dist) return fail(LBIMP_E_INVALID, "null pointer");
     RaggedPlan plan;
     if (int r = plan_ragged(ctx, dbs, ndb, offsets, db_of, w, Q, p, k, mode, idx, dist, plan)) return r;
+    if (ctx->autotune) {  // tune each group shape met for the first time, then plan again with the choices
+        bool tuned_any = false;
+        for (size_t g = 0; g < plan.specs.size(); ++g) {
+            const SearchSpec &sp = plan.specs[g];
+            if (sp.db->N == 0 || ctx->tuned.count(tune_key(sp.db, sp.Q, sp.w, p, k, mode))) continue;
+            const std::vector<int64_t> &ids = std::next(plan.groups.begin(), g)->second;
+            std::vector<int64_t> off(ids.size());
+            for (size_t i = 0; i < ids.size(); ++i) off[i] = offsets[ids[i]];
+            Knobs kn;
+            if (int r = tune_search(ctx, sp.db, nullptr, queries, off.data(), sp.Q, sp.w, p, k, mode, &kn)) return r;
+            tuned_any = true;
+        }
+        if (tuned_any) {
+            plan = RaggedPlan();
+            if (int r = plan_ragged(ctx, dbs, ndb, offsets, db_of, w, Q, p, k, mode, idx, dist, plan)) return r;
+        }
+    }
     auto &groups = plan.groups;
     auto &specs = plan.specs;
     auto &dims = plan.dims;
@@ -835,7 +1024,9 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         mix((uint64_t)db->n);
         mix((uint64_t)specs[g].Q);
         mix((uint64_t)specs[g].w);
-        mix((uint64_t)(specs[g].kn.seeds * 1000 + specs[g].kn.sweep_shape * 10 + specs[g].kn.lbi_pipeline));
+        const Knobs &kn = specs[g].kn;
+        mix((uint64_t)(kn.seeds * 100000 + kn.sweep_shape * 1000 + kn.lbi_pipeline * 100 + kn.dtw_group * 10 +
+                       kn.seed_lane));
     }
     if (!ctx->use_graph && width <= 1) {
         if (int r = enqueue_all(ctx->stream)) return r;
@@ -878,6 +1069,23 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
             const std::vector<int64_t> &ids = std::next(groups.begin(), g)->second;
             fill_stats(dims[g], specs[g].Q, h.data(), ids.data(), stats);
         }
+    }
+    return LBIMP_OK;
+}
+
+int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
+                   int32_t k, int32_t mode, int32_t *choice) {
+    if (int r = check_ctx(ctx)) return r;
+    if (!db) return fail(LBIMP_E_INVALID, "null database");
+    if (db->device != ctx->device) return fail(LBIMP_E_INVALID, "database lives on another device");
+    if (int r = check_search(Q, db->n, w, p, k, mode)) return r;
+    if (Q == 0 || db->N == 0) return fail(LBIMP_E_INVALID, "nothing to tune (no queries or empty database)");
+    if (!queries) return fail(LBIMP_E_INVALID, "null pointer");
+    Knobs kn;
+    if (int r = tune_search(ctx, db, queries, nullptr, nullptr, Q, band_of(db->n, w), p, k, mode, &kn)) return r;
+    if (choice) {
+        const std::array<int, 5> v = knob_values(kn);
+        for (int i = 0; i < 5; ++i) choice[i] = v[i];
     }
     return LBIMP_OK;
 }

@@ -60,7 +60,9 @@ SIGNATURES = {
                                                         ctypes.POINTER(_i32), _i64, _i32, _i32, _i32,
                                                         ctypes.POINTER(ctypes.c_uint64)]),
     "lbimp_ctx_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "lbimp_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32)]),
 }
+TUNE_KNOBS = ("seeds", "sweep_shape", "lbi_pipeline", "dtw_group", "seed_lane")
 
 _lib = None
 
@@ -297,3 +299,13 @@ def lbimp_ctx_workspace_bytes(ctx: Ctx) -> int:
     out = ctypes.c_uint64(0)
     _check(_lib.lbimp_ctx_workspace_bytes(ctx.h, ctypes.byref(out)), "lbimp_ctx_workspace_bytes")
     return int(out.value)
+
+
+def lbimp_autotune(ctx: Ctx, db: Db, queries: torch.Tensor, w: int, p: int, k: int = 1, mode="improved") -> dict:
+    """Tune the search of this batch shape; returns the chosen knobs by name."""
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    out = (_i32 * len(TUNE_KNOBS))()
+    _check(_lib.lbimp_autotune(ctx.sync_stream(), db.h, _dev(queries, "queries"), queries.shape[0], w, p, k, mode,
+                               out), "lbimp_autotune")
+    return {name: int(out[i]) for i, name in enumerate(TUNE_KNOBS)}

@@ -1,0 +1,71 @@
+"""GPU autotuner: the chosen knobs are valid, and results under them are bit-identical to the
+untuned search (the choices change speed only), for homogeneous and ragged batches, narrow
+and wide bands."""
+import numpy as np
+import pytest
+import torch
+
+from paper_0811_3301_amd import gen
+from tests.test_gpu_parity import L, _say, check_knn, f32, to_dev  # noqa: F401  (fixtures)
+
+pytestmark = pytest.mark.gpu
+
+
+def _walks(count, n, seed):
+    return f32(gen.random_walk(count, n, gen.rng(700, 0, seed))).astype(np.float64)
+
+
+@pytest.mark.parametrize("n,w,mode,k", [(128, 13, "improved", 1), (256, 26, "keogh", 5), (128, 13, "brute", 1),
+                                        (300, 80, "improved", 1), (256, 51, "improved", 3)])
+def test_autotune_choice_keeps_results(L, n, w, mode, k):
+    _say(f"autotune n={n} w={w} mode={mode} k={k}")
+    X = _walks(3000, n, n + w)
+    Ys = _walks(24, n, 2 * n + w)
+    ctx = L.Ctx(0)
+    try:
+        db = L.Db(ctx, to_dev(X))
+        Yd = to_dev(Ys)
+        ref_i, ref_d, ref_s = L.lbimp_nn_search(ctx, db, Yd, w, 1, k, mode)
+        choice = L.lbimp_autotune(ctx, db, Yd, w, 1, k, mode)
+        assert choice["seeds"] in (8, 16, 32, 64) and 0 <= choice["sweep_shape"] <= 5
+        assert all(choice[key] in (0, 1) for key in ("lbi_pipeline", "dtw_group", "seed_lane"))
+        got_i, got_d, got_s = L.lbimp_nn_search(ctx, db, Yd, w, 1, k, mode)  # runs with the tuned choice
+        assert torch.equal(ref_i, got_i)
+        assert np.array_equal(ref_d.cpu().numpy().view(np.uint32), got_d.cpu().numpy().view(np.uint32))
+        assert np.array_equal(ref_s[:, 0], got_s[:, 0])
+        check_knn(X, Ys[:4], w, 1, k, got_i.cpu().numpy()[:4], got_d.cpu().numpy()[:4], "tuned")
+        torch.cuda.synchronize()
+        db.close()
+    finally:
+        ctx.close()
+
+
+def test_autotune_option_on_ragged_batch(L):
+    _say("autotune option on a ragged batch")
+    lengths, sizes = [64, 200], [2500, 1500]
+    Xs = [_walks(N, n, 80 + n) for N, n in zip(sizes, lengths)]
+    r = gen.rng(701, 0, 0)
+    Q = 40
+    db_of = r.integers(0, 2, Q).astype(np.int32)
+    w = np.array([(6, 13)[r.integers(0, 2)] if b == 0 else (20, 70)[r.integers(0, 2)] for b in db_of], np.int32)
+    Ys = [_walks(1, lengths[b], 900 + q)[0] for q, b in enumerate(db_of)]
+    offsets = np.zeros(Q + 1, np.int64)
+    offsets[1:] = np.cumsum([len(y) for y in Ys])
+    packed = to_dev(np.concatenate(Ys))
+    ctx = L.Ctx(0)
+    try:
+        dbs = [L.Db(ctx, to_dev(X)) for X in Xs]
+        ref = L.lbimp_nn_search_ragged(ctx, dbs, packed, offsets, db_of, w, 1, 2, "improved")
+        L.lbimp_ctx_set_option(ctx, "autotune", 1)
+        for _ in range(3):  # the first call tunes every group; later calls replay the tuned graph
+            got = L.lbimp_nn_search_ragged(ctx, dbs, packed, offsets, db_of, w, 1, 2, "improved")
+            assert torch.equal(ref[0], got[0])
+            assert np.array_equal(ref[1].cpu().numpy().view(np.uint32), got[1].cpu().numpy().view(np.uint32))
+        for q in range(0, Q, 7):
+            check_knn(Xs[db_of[q]], Ys[q][None, :], int(w[q]), 1, 2, got[0].cpu().numpy()[q:q + 1],
+                      got[1].cpu().numpy()[q:q + 1], f"ragged tuned q={q}")
+        torch.cuda.synchronize()
+        for d in dbs:
+            d.close()
+    finally:
+        ctx.close()
