@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
+    ap.add_argument("--only", choices=("ragged", "serving"),
+                    help="run only the uneven-batch or the serving measurement and print its JSON (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (no multi-GPU path is built)",
@@ -255,6 +257,12 @@ def main():
         return
 
     L.load()
+    if args.only == "ragged":
+        print(json.dumps(ragged_bench(L, args.steps, args.warmup)), flush=True)
+        return
+    if args.only == "serving":
+        print(json.dumps(serving_bench(L, rates=(10_000,), seconds=0.3)), flush=True)
+        return
     N, n, Q, w = 100_000, 256, 256, 26
     log("generating workload")
     db64, qs64 = gen.make_workload("rw256")
@@ -314,7 +322,7 @@ def main():
     serving = None
     if not (args.quick or args.no_serving):
         log("serving loop")
-        serving = serving_bench(L, rates=(1_000, 10_000, 50_000), seconds=0.5)
+        serving = serving_bench(L, rates=(1_000, 10_000, 20_000, 35_000, 50_000), seconds=0.5)
 
     cpu = None
     if not args.no_cpu:
