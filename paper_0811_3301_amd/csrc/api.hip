@@ -301,7 +301,7 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         PairList all{nullptr, 0, nullptr, N};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, all, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
                           k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, nullptr, nullptr, false, false, b.ring,
-                          d.ring_bytes, s));
+                          d.ring_bytes, nullptr, 0, s));
     } else {
         // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
         HIPTRY(launch_lbk_sweep(p, sp.kn.sweep_shape, db->il, N, d.n4, reinterpret_cast<float4 *>(b.Ue),
@@ -316,7 +316,7 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         PairList seedl{b.seeds, d.S, nullptr, d.S};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, seedl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
                           k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, seed_ll, b.ring,
-                          d.ring_bytes, s));
+                          d.ring_bytes, nullptr, 0, s));
         if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, b.thr, s));
         stage(4);
         HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
@@ -333,7 +333,7 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, dtw_ll), b.prefix, s));
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
                           k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, dtw_ll, b.ring,
-                          d.ring_bytes, s));
+                          d.ring_bytes, b.S1, d.Np, s));
     }
     stage(7);
     if (k == 1)
@@ -881,7 +881,7 @@ int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, in
     PairList pl{nullptr, 0, nullptr, N};
     // no threshold: nothing is abandoned and nothing appended (out_root receives every distance)
     HIPTRY(launch_dtw(p, x, n, wb, qd, pl, prefix, 1, ctr, persistent_grid(ctx), nullptr, nothr, nullptr, 0,
-                      nullptr, nullptr, dist, false, ll, ring, ring_bytes, s));
+                      nullptr, nullptr, dist, false, ll, ring, ring_bytes, nullptr, 0, s));
     return LBIMP_OK;
 }
 

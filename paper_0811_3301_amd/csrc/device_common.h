@@ -160,7 +160,28 @@ struct DtwArgs {
     float *out_root;
     bool abandon;
     const u64 *tkeys;  // [Q] abandon thresholds: best (k = 1) or thr (k > 1); always a valid array
+    const float *S1;   // [Q][ldS] LB_Keogh^p of every pair (tightens the abandon bound), or nullptr
+    int64_t ldS;
 };
+
+// Lower bound of a pair's DTW_p once rows 0..i are done: the minimum of row i plus the
+// LB_Keogh^p terms of the rows after i, which every remaining step of a path pays at least
+// (a cell (r, j) costs d(x_r, y_j)^p >= d(x_r, [L_r, U_r])^p).  The tail is S1 (the sweep's
+// sum over all rows) minus the rows already done.  Summation-order rounding of both sums and
+// of the DP itself is below (3n + 4) ulp of the final value (each term is at most the final
+// DTW, S1 included), so the sum is scaled down by (3n + 10) ulp: the bound never exceeds the
+// DTW computed in fp32, and abandoning on it changes no result.
+__device__ __forceinline__ float cascade_bound(float rowmin, float s1, float done, float shrink) {
+    return (rowmin + fmaxf(s1 - done, 0.f)) * shrink;
+}
+__host__ __device__ inline float cascade_shrink(int n) { return 1.f - (3.f * n + 10.f) * 5.9604645e-8f; }
+
+// LB_Keogh^p term of one element against the envelope [lo, hi].
+template <int P>
+__device__ __forceinline__ float lbk_term(float x, float lo, float hi) {
+    const float d = x - __builtin_amdgcn_fmed3f(x, lo, hi);
+    return (P == 1) ? fabsf(d) : d * d;
+}
 
 // Arguments of the register-state LB_Improved kernels (one instantiation per half-width).
 struct LbiArgs {

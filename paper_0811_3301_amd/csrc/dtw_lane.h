@@ -58,10 +58,13 @@ __device__ __forceinline__ void dtw_rows4(float (&D)[2 * W + 1], const float (&x
 template <int P, int W>
 __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
     constexpr int BW = 2 * W + 1;
-    extern __shared__ float ypad[];  // ypad[t] = y[t - W], +inf outside [0, n)
+    extern __shared__ float ypad[];  // ypad[t] = y[t - W], +inf outside [0, n); then U, L when a.S1
     const int lane = threadIdx.x;
     const int n = a.n;
     const int plen = n + BW + 4;
+    float *sU = ypad + plen, *sL = sU + n;
+    const bool cascade = a.S1 != nullptr;
+    const float shrink = cascade_shrink(n);
     int64_t cur_q = -1;
     int64_t q;
     long long b;
@@ -74,6 +77,10 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
                 const int j = t - W;
                 return (j >= 0 && j < n) ? y[j] : kInf;
             });
+            if (cascade) {
+                stage_lds(sU, n, [&](int t) { return a.qd.U[q * a.qd.ldq + t]; });
+                stage_lds(sL, n, [&](int t) { return a.qd.L[q * a.qd.ldq + t]; });
+            }
             __syncthreads();
             cur_q = q;
         }
@@ -97,6 +104,8 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
         // with no branch around the load, so the wait for it lands where it is used.
         const u64 *tq = a.tkeys + q;
         u64 tcur = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const float s1v = cascade ? a.S1[q * a.ldS + c] : 0.f;
+        float done = 0.f;  // LB_Keogh^p terms of the rows already computed
         for (; i0 < nfull; i0 += 4) {
             float xn[4];
             const int inext = i0 + 4 < nfull ? i0 + 4 : i0;  // prefetch the next 4 rows
@@ -104,12 +113,17 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
             for (int r = 0; r < 4; ++r) xn[r] = x[inext + r];
             const u64 tnext = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             dtw_rows4<P, W>(D, xs, ypad + i0);
+            if (cascade) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) done += lbk_term<P>(xs[r], sL[i0 + r], sU[i0 + r]);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) xs[r] = xn[r];
             if (a.abandon) {
                 float mn = D[0];
 #pragma unroll
                 for (int k = 1; k < BW; ++k) mn = fminf(mn, D[k]);
+                if (cascade) mn = cascade_bound(mn, s1v, done, shrink);
                 if (active && make_key(mn, c) >= tcur) {
                     active = false;
                     ++stopped;
@@ -129,8 +143,13 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
 }
 
 template <int P, int W>
-static void dtw_lane_launch(int num_cu, const DtwArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float) * (size_t)(a.n + 2 * W + 1 + 4);
+static void dtw_lane_launch(int num_cu, const DtwArgs &a_in, hipStream_t s) {
+    DtwArgs a = a_in;
+    auto lds_of = [&](bool cascade) {
+        return sizeof(float) * ((size_t)a.n + 2 * W + 1 + 4 + (cascade ? 2 * (size_t)a.n : 0));
+    };
+    if (a.S1 && lds_of(true) > kLdsBudget) a.S1 = nullptr;  // no room for U, L: row minimum only
+    const size_t lds = lds_of(a.S1 != nullptr);
     hipLaunchKernelGGL((k_dtw_lane<P, W>), dim3(persistent_grid(k_dtw_lane<P, W>, lds, num_cu)), dim3(64), lds, s,
                        a);
 }

@@ -80,11 +80,14 @@ __device__ __forceinline__ float strip_col1(float (&R)[C], const float (&X)[C], 
 
 template <int P, int C>
 __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__restrict__ ring_base, int rb_log2) {
-    extern __shared__ float ypad[];  // ypad[j + w + 4] = y[j] for 0 <= j < n, -inf elsewhere
+    extern __shared__ float ypad[];  // ypad[j + w + 4] = y[j] for 0 <= j < n, -inf elsewhere; then U, L
     const int lane = threadIdx.x;
     const int n = a.n;
     const int yoff = w + 4;
     const int plen = n + 2 * w + 8;
+    float *sU = ypad + plen, *sL = sU + n;
+    const bool cascade = a.S1 != nullptr;
+    const float shrink = cascade_shrink(n);
     const int rmask = (1 << rb_log2) - 1;
     float *ring = ring_base + ((size_t)blockIdx.x << rb_log2) * 64 + lane;  // slot j at ring[(j & rmask) * 64]
     const int S = (n + C - 1) / C;
@@ -101,6 +104,10 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
                 const int j = t - yoff;
                 return (j >= 0 && j < n) ? y[j] : -kInf;
             });
+            if (cascade) {
+                stage_lds(sU, n, [&](int t) { return a.qd.U[q * a.qd.ldq + t]; });
+                stage_lds(sL, n, [&](int t) { return a.qd.L[q * a.qd.ldq + t]; });
+            }
             __syncthreads();
             cur_q = q;
         }
@@ -112,6 +119,8 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
         const u64 *tq = a.tkeys + q;
         int stopped = 0;
         float fin = kInf;
+        const float s1v = cascade ? a.S1[q * a.ldS + c] : 0.f;
+        float done = 0.f;  // LB_Keogh^p terms of the rows already computed
         for (int s = 0; s < S; ++s) {
             const int I0 = I00 + s * C;
             float X[C], R[C];
@@ -214,6 +223,12 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
             LBIMP_STRIP_RIGHT(12) LBIMP_STRIP_RIGHT(13) LBIMP_STRIP_RIGHT(14) LBIMP_STRIP_RIGHT(15)
 #undef LBIMP_STRIP_RIGHT
             if (a.abandon && s + 1 < S) {
+                if (cascade) {
+#pragma unroll
+                    for (int r = 0; r < C; ++r)
+                        if (I0 + r >= 0) done += lbk_term<P>(X[r], sL[I0 + r], sU[I0 + r]);
+                    cmin = cascade_bound(cmin, s1v, done, shrink);
+                }
                 if (active && make_key(cmin, c) >= th) {
                     active = false;
                     stopped = 1;
@@ -237,7 +252,10 @@ static int ring_log2(int w) {
     return l;
 }
 
-static size_t strip_lds(int n, int w) { return sizeof(float) * (size_t)(n + 2 * w + 8); }
+// LDS: the padded query, then (with the tighter abandon bound) its envelope U, L.
+static size_t strip_lds(int n, int w, bool cascade = false) {
+    return sizeof(float) * ((size_t)n + 2 * (size_t)w + 8 + (cascade ? 2 * (size_t)n : 0));
+}
 
 template <int P>
 static int strip_grid(int n, int w, int num_cu) {
@@ -250,19 +268,22 @@ size_t dtw_strip_scratch(int p, int n, int w, int num_cu) {
     return sizeof(float) * (size_t)grid * ((size_t)1 << ring_log2(w)) * 64;
 }
 
-hipError_t launch_dtw_strip(int p, int w, int num_cu, const DtwArgs &a, float *ring, size_t ring_bytes,
+hipError_t launch_dtw_strip(int p, int w, int num_cu, const DtwArgs &a_in, float *ring, size_t ring_bytes,
                             hipStream_t s) {
     static_assert(kStripRows <= kLaneMaxW + 1, "strips need w >= C");
-    if (w <= kLaneMaxW || !ring || ring_bytes < dtw_strip_scratch(p, a.n, w, num_cu)) return hipErrorInvalidValue;
-    const size_t lds = strip_lds(a.n, w);
+    if (w <= kLaneMaxW || !ring || ring_bytes < dtw_strip_scratch(p, a_in.n, w, num_cu)) return hipErrorInvalidValue;
+    DtwArgs a = a_in;
+    if (a.S1 && strip_lds(a.n, w, true) > kLdsBudget) a.S1 = nullptr;  // no room for U, L: row minimum only
+    const size_t lds = strip_lds(a.n, w, a.S1 != nullptr);
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     const int rl = ring_log2(w);
+    // the ring was sized for the grid without U, L in LDS, which is at least as large
     if (p == 1)
-        hipLaunchKernelGGL((k_dtw_strip<1, kStripRows>), dim3(strip_grid<1>(a.n, w, num_cu)), dim3(64), lds, s, a, w,
-                           ring, rl);
+        hipLaunchKernelGGL((k_dtw_strip<1, kStripRows>), dim3(persistent_grid(k_dtw_strip<1, kStripRows>, lds, num_cu)),
+                           dim3(64), lds, s, a, w, ring, rl);
     else
-        hipLaunchKernelGGL((k_dtw_strip<2, kStripRows>), dim3(strip_grid<2>(a.n, w, num_cu)), dim3(64), lds, s, a, w,
-                           ring, rl);
+        hipLaunchKernelGGL((k_dtw_strip<2, kStripRows>), dim3(persistent_grid(k_dtw_strip<2, kStripRows>, lds, num_cu)),
+                           dim3(64), lds, s, a, w, ring, rl);
     return hipGetLastError();
 }
 

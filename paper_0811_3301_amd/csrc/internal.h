@@ -92,6 +92,8 @@ hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, 
 // out_root (single query): out_root[c] = DTW_p.  abandon=false computes every DTW in full.
 // low_latency: a group of lanes per pair (few pairs, each finished quickly) instead of a lane
 // per pair (many pairs, highest throughput).  Items hold dtw_batch(n, w, low_latency) pairs.
+// S1 (optional, [Q][ldS]): LB_Keogh^p of every pair against the query envelope qd.U/qd.L; the
+// lane-per-pair kernels then abandon on the row minimum plus the LB_Keogh terms still to come.
 // Lane-per-pair DTW of bands wider than kLaneMaxW keeps a per-wave ring of strip boundaries
 // in `ring` (device scratch of at least dtw_strip_scratch(p, n, w, num_cu) bytes; 0 bytes
 // when the band is narrow enough or low_latency is set).
@@ -100,7 +102,8 @@ size_t dtw_strip_scratch(int p, int n, int w, int num_cu);
 hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const long long *prefix,
                       int64_t Q, int *ctr, int num_cu, unsigned long long *best, const unsigned long long *thr,
                       unsigned long long *res, int64_t ldres, int *rescnt, int *abandoned, float *out_root,
-                      bool abandon, bool low_latency, float *ring, size_t ring_bytes, hipStream_t s);
+                      bool abandon, bool low_latency, float *ring, size_t ring_bytes, const float *S1,
+                      int64_t ldS, hipStream_t s);
 
 // k-th smallest key of res[q][0..min(rescnt[q], 64)) into thr[q] (kNoKey if fewer than k).
 hipError_t launch_kth_key(const unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k,
