@@ -177,10 +177,15 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
  * to a power of two) in lbimp_nn_search and lbimp_nn_search_ragged.  With the context option
  * "autotune" set, those calls tune a shape they meet for the first time by themselves.
  * choice: host [LBIMP_TUNE_KNOBS] or NULL, receives {seeds, sweep_shape, lbi_pipeline,
- * survivors' DTW group-per-pair, seeding DTW lane-per-pair}.  Waits for the stream. */
-#define LBIMP_TUNE_KNOBS 5
+ * survivors' DTW group-per-pair, seeding DTW lane-per-pair, abandon bound with the LB_Keogh
+ * tail}.  Waits for the stream. */
+#define LBIMP_TUNE_KNOBS 6
 int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                    int32_t k, int32_t mode, int32_t *choice);
+
+/* Copy every tuned choice of `src` into `dst` (same device), e.g. to tune once and share the
+ * result among the contexts of a serving loop.  Entries of dst for other shapes are kept. */
+int lbimp_ctx_copy_tuning(lbimp_ctx *dst, const lbimp_ctx *src);
 
 /* Device workspace (bytes) that a context allocates to run lbimp_nn_search_ragged on this
  * batch (same arguments; query lengths are taken from the databases), written to *bytes.

@@ -46,6 +46,7 @@ namespace {
 constexpr int kStages = 8;
 constexpr int kMaxSeeds = 64;
 constexpr int kPoolStreams = 4;  // concurrent groups of a ragged batch
+constexpr int kTuneKnobs = LBIMP_TUNE_KNOBS;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -110,7 +111,7 @@ struct lbimp_ctx {
     uint64_t graph_sig = 0;
     std::vector<PinnedChunk> pinned;  // ring of staging buffers, each reusable once its upload ran
     bool autotune = false;            // option "autotune"
-    std::map<TuneKey, std::array<int, 5>> tuned;  // seeds, sweep_shape, lbi_pipeline, dtw_group, seed_lane
+    std::map<TuneKey, std::array<int, kTuneKnobs>> tuned;  // in the order of LBIMP_TUNE_KNOBS
     hipEvent_t tev[2] = {};
     hipEvent_t ev[kStages + 1] = {};
 };
@@ -177,6 +178,7 @@ struct Knobs {
     int sweep_shape;    // tiling of the LB_Keogh sweep
     bool dtw_group;     // survivors' DTW with a group of lanes per pair (else a lane per pair)
     bool seed_lane;     // seeding DTWs with a lane per pair (else a group of lanes per pair)
+    bool cascade;       // abandon on the row minimum plus the LB_Keogh terms still to come
 };
 
 struct SearchSpec {  // Q queries of one length against one database
@@ -329,11 +331,11 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
             dl = PairList{b.list2, N, cnt2, 0};
         }
         stage(6);
-        const bool dtw_ll = sp.kn.dtw_group && wb <= kLaneMaxW;
+        const bool dtw_ll = sp.kn.dtw_group && (wb <= kLaneMaxW || dtw_wavereg_wide_supported(n, wb));
         HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, dtw_ll), b.prefix, s));
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
                           k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, dtw_ll, b.ring,
-                          d.ring_bytes, b.S1, d.Np, s));
+                          d.ring_bytes, sp.kn.cascade ? b.S1 : nullptr, d.Np, s));
     }
     stage(7);
     if (k == 1)
@@ -345,19 +347,20 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
 }
 
 static Knobs ctx_knobs(const lbimp_ctx *ctx) {
-    return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false};
+    return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false, true};
 }
 
 static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int mode) {
     return TuneKey{db->N, db->n, wb, p, k, mode, pow2_at_least(Q)};
 }
 
-static Knobs knobs_of(const std::array<int, 5> &v) {
-    return Knobs{v[0], v[2] != 0, v[1], v[3] != 0, v[4] != 0};
+static Knobs knobs_of(const std::array<int, kTuneKnobs> &v) {
+    return Knobs{v[0], v[2] != 0, v[1], v[3] != 0, v[4] != 0, v[5] != 0};
 }
 
-static std::array<int, 5> knob_values(const Knobs &k) {
-    return {k.seeds, k.sweep_shape, k.lbi_pipeline ? 1 : 0, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0};
+static std::array<int, kTuneKnobs> knob_values(const Knobs &k) {
+    return {k.seeds, k.sweep_shape, k.lbi_pipeline ? 1 : 0, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0,
+            k.cascade ? 1 : 0};
 }
 
 // The tuned choice for this batch shape if there is one, else the context's options.
@@ -385,7 +388,8 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     size_t search_bytes = 0;
     for (int sd : seed_opts)
         for (int sh : shape_opts) {
-            SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr, Knobs{sd, true, sh, false, false}};
+            SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr,
+                          Knobs{sd, true, sh, false, false, true}};
             SearchDims d;
             if (int r = dims_of(sp, ctx->num_cu, d)) return r;
             SearchBufs b;
@@ -470,7 +474,7 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
         kn.seed_lane = !kn.seed_lane;
         if (int r = consider(kn)) return r;
     }
-    if (wb <= kLaneMaxW) {
+    if (wb <= kLaneMaxW || dtw_wavereg_wide_supported(db->n, wb)) {
         Knobs kn = best;
         kn.dtw_group = !kn.dtw_group;
         if (int r = consider(kn)) return r;
@@ -478,6 +482,11 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     if (improved && wb <= kLbiRegMaxW) {
         Knobs kn = best;
         kn.lbi_pipeline = !kn.lbi_pipeline;
+        if (int r = consider(kn)) return r;
+    }
+    if (!brute) {
+        Knobs kn = best;
+        kn.cascade = !kn.cascade;
         if (int r = consider(kn)) return r;
     }
     ctx->tuned[tune_key(db, Q, wb, p, k, mode)] = knob_values(best);
@@ -1025,8 +1034,8 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         mix((uint64_t)specs[g].Q);
         mix((uint64_t)specs[g].w);
         const Knobs &kn = specs[g].kn;
-        mix((uint64_t)(kn.seeds * 100000 + kn.sweep_shape * 1000 + kn.lbi_pipeline * 100 + kn.dtw_group * 10 +
-                       kn.seed_lane));
+        mix((uint64_t)(kn.seeds * 1000000 + kn.sweep_shape * 10000 + kn.lbi_pipeline * 1000 + kn.dtw_group * 100 +
+                       kn.seed_lane * 10 + kn.cascade));
     }
     if (!ctx->use_graph && width <= 1) {
         if (int r = enqueue_all(ctx->stream)) return r;
@@ -1084,9 +1093,16 @@ int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int
     Knobs kn;
     if (int r = tune_search(ctx, db, queries, nullptr, nullptr, Q, band_of(db->n, w), p, k, mode, &kn)) return r;
     if (choice) {
-        const std::array<int, 5> v = knob_values(kn);
-        for (int i = 0; i < 5; ++i) choice[i] = v[i];
+        const std::array<int, kTuneKnobs> v = knob_values(kn);
+        for (int i = 0; i < kTuneKnobs; ++i) choice[i] = v[i];
     }
+    return LBIMP_OK;
+}
+
+int lbimp_ctx_copy_tuning(lbimp_ctx *dst, const lbimp_ctx *src) {
+    if (!dst || !src) return fail(LBIMP_E_INVALID, "null context");
+    if (dst->device != src->device) return fail(LBIMP_E_INVALID, "contexts on different devices");
+    for (const auto &kv : src->tuned) dst->tuned[kv.first] = kv.second;
     return LBIMP_OK;
 }
 

@@ -214,6 +214,10 @@ hipError_t launch_lbi_reg_p2(int w, int num_cu, const LbiArgs &a, hipStream_t s)
 int dtw_wave_batch(int n, int w);
 hipError_t launch_dtw_wavereg(int p, int w, int num_cu, const DtwArgs &a, hipStream_t s);
 
+// Group-per-pair DTW for 63 < w < 512: one pair per wave, several band positions per lane.
+bool dtw_wavereg_wide_supported(int n, int w);
+hipError_t launch_dtw_wavereg_wide(int p, int w, int num_cu, const DtwArgs &a, hipStream_t s);
+
 // Lane-per-pair DTW of wide bands in strips of rows (ring: per-wave strip boundaries).
 hipError_t launch_dtw_strip(int p, int w, int num_cu, const DtwArgs &a, float *ring, size_t ring_bytes,
                             hipStream_t s);

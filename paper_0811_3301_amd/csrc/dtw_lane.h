@@ -55,7 +55,7 @@ __device__ __forceinline__ void dtw_rows4(float (&D)[2 * W + 1], const float (&x
     }
 }
 
-template <int P, int W>
+template <int P, int W, bool CASCADE>
 __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
     constexpr int BW = 2 * W + 1;
     extern __shared__ float ypad[];  // ypad[t] = y[t - W], +inf outside [0, n); then U, L when a.S1
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
     const int n = a.n;
     const int plen = n + BW + 4;
     float *sU = ypad + plen, *sL = sU + n;
-    const bool cascade = a.S1 != nullptr;
+    constexpr bool cascade = CASCADE;  // a.S1 is set exactly for this instantiation
     const float shrink = cascade_shrink(n);
     int64_t cur_q = -1;
     int64_t q;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
                 const int j = t - W;
                 return (j >= 0 && j < n) ? y[j] : kInf;
             });
-            if (cascade) {
+            if constexpr (cascade) {
                 stage_lds(sU, n, [&](int t) { return a.qd.U[q * a.qd.ldq + t]; });
                 stage_lds(sL, n, [&](int t) { return a.qd.L[q * a.qd.ldq + t]; });
             }
@@ -104,7 +104,8 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
         // with no branch around the load, so the wait for it lands where it is used.
         const u64 *tq = a.tkeys + q;
         u64 tcur = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const float s1v = cascade ? a.S1[q * a.ldS + c] : 0.f;
+        float s1v = 0.f;
+        if constexpr (cascade) s1v = a.S1[q * a.ldS + c];
         float done = 0.f;  // LB_Keogh^p terms of the rows already computed
         for (; i0 < nfull; i0 += 4) {
             float xn[4];
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
             for (int r = 0; r < 4; ++r) xn[r] = x[inext + r];
             const u64 tnext = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             dtw_rows4<P, W>(D, xs, ypad + i0);
-            if (cascade) {
+            if constexpr (cascade) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) done += lbk_term<P>(xs[r], sL[i0 + r], sU[i0 + r]);
             }
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
                 float mn = D[0];
 #pragma unroll
                 for (int k = 1; k < BW; ++k) mn = fminf(mn, D[k]);
-                if (cascade) mn = cascade_bound(mn, s1v, done, shrink);
+                if constexpr (cascade) mn = cascade_bound(mn, s1v, done, shrink);
                 if (active && make_key(mn, c) >= tcur) {
                     active = false;
                     ++stopped;
@@ -150,8 +151,12 @@ static void dtw_lane_launch(int num_cu, const DtwArgs &a_in, hipStream_t s) {
     };
     if (a.S1 && lds_of(true) > kLdsBudget) a.S1 = nullptr;  // no room for U, L: row minimum only
     const size_t lds = lds_of(a.S1 != nullptr);
-    hipLaunchKernelGGL((k_dtw_lane<P, W>), dim3(persistent_grid(k_dtw_lane<P, W>, lds, num_cu)), dim3(64), lds, s,
-                       a);
+    if (a.S1)
+        hipLaunchKernelGGL((k_dtw_lane<P, W, true>), dim3(persistent_grid(k_dtw_lane<P, W, true>, lds, num_cu)),
+                           dim3(64), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_dtw_lane<P, W, false>), dim3(persistent_grid(k_dtw_lane<P, W, false>, lds, num_cu)),
+                           dim3(64), lds, s, a);
 }
 
 using DtwLaneFn = void (*)(int, const DtwArgs &, hipStream_t);

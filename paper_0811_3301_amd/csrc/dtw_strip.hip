@@ -18,6 +18,7 @@
 // (it has no left phase when w >= C).  Requires w >= C.
 // Early abandoning: every path crosses each row, so after a strip the minimum of its last
 // row over the band bounds the result.
+#include <algorithm>
 #include <climits>
 
 #include "device_common.h"
@@ -78,7 +79,7 @@ __device__ __forceinline__ float strip_col1(float (&R)[C], const float (&X)[C], 
     return R[C - 1];
 }
 
-template <int P, int C>
+template <int P, int C, bool CASCADE>
 __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__restrict__ ring_base, int rb_log2) {
     extern __shared__ float ypad[];  // ypad[j + w + 4] = y[j] for 0 <= j < n, -inf elsewhere; then U, L
     const int lane = threadIdx.x;
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
     const int yoff = w + 4;
     const int plen = n + 2 * w + 8;
     float *sU = ypad + plen, *sL = sU + n;
-    const bool cascade = a.S1 != nullptr;
+    constexpr bool cascade = CASCADE;  // a.S1 is set exactly for this instantiation
     const float shrink = cascade_shrink(n);
     const int rmask = (1 << rb_log2) - 1;
     float *ring = ring_base + ((size_t)blockIdx.x << rb_log2) * 64 + lane;  // slot j at ring[(j & rmask) * 64]
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
                 const int j = t - yoff;
                 return (j >= 0 && j < n) ? y[j] : -kInf;
             });
-            if (cascade) {
+            if constexpr (cascade) {
                 stage_lds(sU, n, [&](int t) { return a.qd.U[q * a.qd.ldq + t]; });
                 stage_lds(sL, n, [&](int t) { return a.qd.L[q * a.qd.ldq + t]; });
             }
@@ -119,7 +120,8 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
         const u64 *tq = a.tkeys + q;
         int stopped = 0;
         float fin = kInf;
-        const float s1v = cascade ? a.S1[q * a.ldS + c] : 0.f;
+        float s1v = 0.f;
+        if constexpr (cascade) s1v = a.S1[q * a.ldS + c];
         float done = 0.f;  // LB_Keogh^p terms of the rows already computed
         for (int s = 0; s < S; ++s) {
             const int I0 = I00 + s * C;
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
             LBIMP_STRIP_RIGHT(12) LBIMP_STRIP_RIGHT(13) LBIMP_STRIP_RIGHT(14) LBIMP_STRIP_RIGHT(15)
 #undef LBIMP_STRIP_RIGHT
             if (a.abandon && s + 1 < S) {
-                if (cascade) {
+                if constexpr (cascade) {
 #pragma unroll
                     for (int r = 0; r < C; ++r)
                         if (I0 + r >= 0) done += lbk_term<P>(X[r], sL[I0 + r], sU[I0 + r]);
@@ -259,7 +261,7 @@ static size_t strip_lds(int n, int w, bool cascade = false) {
 
 template <int P>
 static int strip_grid(int n, int w, int num_cu) {
-    return persistent_grid(k_dtw_strip<P, kStripRows>, strip_lds(n, w), num_cu);
+    return persistent_grid(k_dtw_strip<P, kStripRows, false>, strip_lds(n, w), num_cu);
 }
 
 size_t dtw_strip_scratch(int p, int n, int w, int num_cu) {
@@ -277,13 +279,22 @@ hipError_t launch_dtw_strip(int p, int w, int num_cu, const DtwArgs &a_in, float
     const size_t lds = strip_lds(a.n, w, a.S1 != nullptr);
     if (lds > kLdsBudget) return hipErrorInvalidValue;
     const int rl = ring_log2(w);
-    // the ring was sized for the grid without U, L in LDS, which is at least as large
-    if (p == 1)
-        hipLaunchKernelGGL((k_dtw_strip<1, kStripRows>), dim3(persistent_grid(k_dtw_strip<1, kStripRows>, lds, num_cu)),
-                           dim3(64), lds, s, a, w, ring, rl);
-    else
-        hipLaunchKernelGGL((k_dtw_strip<2, kStripRows>), dim3(persistent_grid(k_dtw_strip<2, kStripRows>, lds, num_cu)),
-                           dim3(64), lds, s, a, w, ring, rl);
+    // the ring was sized for the grid of the plain kernel without U, L in LDS; the grid launched
+    // here is capped to it
+    const int cap = p == 1 ? strip_grid<1>(a.n, w, num_cu) : strip_grid<2>(a.n, w, num_cu);
+#define LBIMP_STRIP(PP, CC)                                                                                         \
+    hipLaunchKernelGGL((k_dtw_strip<PP, kStripRows, CC>),                                                          \
+                       dim3(std::min(cap, persistent_grid(k_dtw_strip<PP, kStripRows, CC>, lds, num_cu))), dim3(64), \
+                       lds, s, a, w, ring, rl)
+    const bool cas = a.S1 != nullptr;
+    if (p == 1) {
+        if (cas) LBIMP_STRIP(1, true);
+        else LBIMP_STRIP(1, false);
+    } else {
+        if (cas) LBIMP_STRIP(2, true);
+        else LBIMP_STRIP(2, false);
+    }
+#undef LBIMP_STRIP
     return hipGetLastError();
 }
 

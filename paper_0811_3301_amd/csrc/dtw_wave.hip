@@ -133,6 +133,146 @@ __global__ __launch_bounds__(64) void k_dtw_wavereg(DtwArgs a, int w, int LP) {
     }
 }
 
+// Wide bands (63 < w < 64R): one pair per wave, lane l holding the R position pairs
+// (2m, 2m+1) for m = lR + r, r < R.  The recursion is the one above with the neighbours
+// inside a lane read directly: the even cell of position r takes its left value from the odd
+// cell of r-1 (previous step), and only r = 0 takes it from lane l-1 (DPP shift right); the
+// odd cell of r takes its up value from the even cell of r+1 (this step), and only r = R-1
+// from lane l+1 (shift left).  Cell (r) of lane l sits at i = t + (w - (w&1))/2 - (lR + r):
+// over a block of 8 steps a lane reads a window of R+7 x values and R+8 y values from LDS.
+template <int P, int R>
+__global__ __launch_bounds__(64) void k_dtw_wavereg_r(DtwArgs a, int w) {
+    extern __shared__ float sm[];
+    constexpr int pad = 64 * R + 32;
+    const int n = a.n;
+    const int span = n + 2 * pad;
+    float *ys = sm;         // [span], ys[j + pad] = y[j], -inf outside
+    float *xs = sm + span;  // [span], xs[i + pad] = x[i], +inf outside
+    const int lane = threadIdx.x;
+    const int mv = w >> 1;  // position pair holding the start and end cells
+    const bool slot_odd = (w & 1) != 0;
+    const int ibase = (w - (w & 1)) / 2;
+    // x of (lane, r, step t) is x[ibase - (lane*R + r) + t]; y is y[-(w&1) - ibase + lane*R + r + t (+1)]
+    const int xb = pad + ibase - (lane * R + R - 1);
+    const int yb = pad - (w & 1) - ibase + lane * R;
+    int64_t cur_q = -1;
+    int64_t q;
+    long long b;
+    ItemCursor items(a.pl, a.prefix, a.Q, 1);
+    while (items.get(q, b)) {
+        if (b >= pair_count(a.pl, q)) continue;
+        const int c = pair_cand(a.pl, q, b);
+        __syncthreads();
+        if (q != cur_q) {
+            const float *y = a.qd.Y + q * a.qd.ldy;
+            stage_lds(ys, span, [&](int t) {
+                const int j = t - pad;
+                return (j >= 0 && j < n) ? y[j] : -kInf;
+            });
+            cur_q = q;
+        }
+        const float *xrow = a.rows + (int64_t)c * n;
+        stage_lds(xs, span, [&](int t) {
+            const int i = t - pad;
+            return (i >= 0 && i < n) ? xrow[i] : kInf;
+        });
+        __syncthreads();
+        const u64 *tq = a.tkeys + q;
+        float E[R], O[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool here = lane * R + r == mv;
+            E[r] = (here && !slot_odd) ? 0.f : kInf;  // state of step -1: D(-1,-1) = 0 on diagonal -2
+            O[r] = (here && slot_odd) ? 0.f : kInf;
+        }
+        bool alive = true;
+        // steps t0..t0+nb-1 from windows xw[k] = xs[xb + t0 + k], yw[k] = ys[yb + t0 + k]
+        auto block = [&](int t0, int nb) {
+            float xw[R + 7], yw[R + 8];
+#pragma unroll
+            for (int k = 0; k < R + 7; ++k) xw[k] = xs[xb + t0 + k];
+#pragma unroll
+            for (int k = 0; k < R + 8; ++k) yw[k] = ys[yb + t0 + k];
+#pragma unroll
+            for (int st = 0; st < 8; ++st) {
+                if (st < nb) {
+                    const float left0 = dpp_shr1(O[R - 1]);
+#pragma unroll
+                    for (int r = R - 1; r >= 0; --r) {  // descending: O[r-1] still holds the previous step
+                        const float left = (r == 0) ? left0 : O[r - 1];
+                        const float m = __builtin_fminf(__builtin_fminf(left, O[r]), E[r]);
+                        const float v = cost_add<P>(xw[R - 1 - r + st] - yw[r + st], m);
+                        E[r] = 2 * (lane * R + r) <= 2 * w ? v : kInf;
+                    }
+                    const float upl = dpp_shl1(E[0]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float up = (r + 1 < R) ? E[r + 1] : upl;
+                        const float m = __builtin_fminf(__builtin_fminf(E[r], up), O[r]);
+                        const float v = cost_add<P>(xw[R - 1 - r + st] - yw[r + st + 1], m);
+                        O[r] = 2 * (lane * R + r) + 1 <= 2 * w ? v : kInf;
+                    }
+                }
+            }
+        };
+        int t0 = 0;
+        for (; t0 + 8 <= n; t0 += 8) {
+            block(t0, 8);
+            if (a.abandon) {
+                float m = kInf;
+#pragma unroll
+                for (int r = 0; r < R; ++r) m = fminf(m, fminf(E[r], O[r]));
+                for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
+                const u64 th = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (make_key(m, c) >= th) {
+                    alive = false;
+                    break;
+                }
+            }
+        }
+        if (alive && t0 < n) block(t0, n - t0);
+        float dfin = kInf;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (lane * R + r == mv) dfin = slot_odd ? O[r] : E[r];
+        const bool owner = lane == mv / R;
+        publish<P>(owner && alive, dfin, c, q, a.best, a.thr, a.res, a.ldres, a.rescnt, a.out_root);
+        if (a.abandoned && owner && !alive) atomicAdd(&a.abandoned[q], 1);
+    }
+}
+
+// Position pairs per lane for a wide band (0: not supported, use the LDS kernel).
+static int wave_r(int w) {
+    for (int r : {2, 4, 8})
+        if (w < 64 * r) return r;
+    return 0;
+}
+
+bool dtw_wavereg_wide_supported(int n, int w) {
+    const int r = wave_r(w);
+    return r > 0 && sizeof(float) * 2 * (size_t)(n + 2 * (64 * r + 32)) <= kLdsBudget;
+}
+
+hipError_t launch_dtw_wavereg_wide(int p, int w, int num_cu, const DtwArgs &a, hipStream_t s) {
+    if (w <= kLaneMaxW || !dtw_wavereg_wide_supported(a.n, w)) return hipErrorInvalidValue;
+    const int r = wave_r(w);
+    const size_t lds = sizeof(float) * 2 * (size_t)(a.n + 2 * (64 * r + 32));
+#define LBIMP_WAVE_R(PP, RR)                                                                                    \
+    hipLaunchKernelGGL((k_dtw_wavereg_r<PP, RR>), dim3(persistent_grid(k_dtw_wavereg_r<PP, RR>, lds, num_cu)), \
+                       dim3(64), lds, s, a, w)
+    if (p == 1) {
+        if (r == 2) LBIMP_WAVE_R(1, 2);
+        else if (r == 4) LBIMP_WAVE_R(1, 4);
+        else LBIMP_WAVE_R(1, 8);
+    } else {
+        if (r == 2) LBIMP_WAVE_R(2, 2);
+        else if (r == 4) LBIMP_WAVE_R(2, 4);
+        else LBIMP_WAVE_R(2, 8);
+    }
+#undef LBIMP_WAVE_R
+    return hipGetLastError();
+}
+
 // Lanes per pair: the smallest power of two above w, widened until the staged rows fit in LDS.
 static int wave_lanes(int n, int w) {
     int lp = 1;

@@ -98,6 +98,7 @@ hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, 
 // in `ring` (device scratch of at least dtw_strip_scratch(p, n, w, num_cu) bytes; 0 bytes
 // when the band is narrow enough or low_latency is set).
 int dtw_batch(int n, int w, bool low_latency);
+bool dtw_wavereg_wide_supported(int n, int w);  // group-per-pair kernel for 63 < w (low_latency)
 size_t dtw_strip_scratch(int p, int n, int w, int num_cu);
 hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const long long *prefix,
                       int64_t Q, int *ctr, int num_cu, unsigned long long *best, const unsigned long long *thr,

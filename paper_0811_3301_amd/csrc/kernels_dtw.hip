@@ -228,11 +228,12 @@ hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, Pair
                       unsigned long long *res, int64_t ldres, int *rescnt, int *abandoned, float *out_root,
                       bool abandon, bool low_latency, float *ring, size_t ring_bytes, const float *S1,
                       int64_t ldS, hipStream_t s) {
-    if (w <= kLaneMaxW || !low_latency) {
+    if (w <= kLaneMaxW || !low_latency || dtw_wavereg_wide_supported(n, w)) {
         const u64 *tkeys = best ? best : thr;
         if (!tkeys) return hipErrorInvalidValue;  // callers pass a threshold array, kNoKey-filled if unused
         DtwArgs a{rows, n, qd, pl, prefix, Q, ctr, best, thr, res, ldres, rescnt, abandoned, out_root, abandon, tkeys,
                   abandon ? S1 : nullptr, ldS};
+        if (w > kLaneMaxW && low_latency) return launch_dtw_wavereg_wide(p, w, num_cu, a, s);
         if (w > kLaneMaxW) return launch_dtw_strip(p, w, num_cu, a, ring, ring_bytes, s);
         if (low_latency) return launch_dtw_wavereg(p, w, num_cu, a, s);
         return p == 1 ? launch_dtw_lane_p1(w, num_cu, a, s) : launch_dtw_lane_p2(w, num_cu, a, s);

@@ -61,8 +61,9 @@ SIGNATURES = {
                                                         ctypes.POINTER(ctypes.c_uint64)]),
     "lbimp_ctx_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
     "lbimp_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32)]),
+    "lbimp_ctx_copy_tuning": (ctypes.c_int, [_vp, _vp]),
 }
-TUNE_KNOBS = ("seeds", "sweep_shape", "lbi_pipeline", "dtw_group", "seed_lane")
+TUNE_KNOBS = ("seeds", "sweep_shape", "lbi_pipeline", "dtw_group", "seed_lane", "cascade")
 
 _lib = None
 
@@ -309,3 +310,7 @@ def lbimp_autotune(ctx: Ctx, db: Db, queries: torch.Tensor, w: int, p: int, k: i
     _check(_lib.lbimp_autotune(ctx.sync_stream(), db.h, _dev(queries, "queries"), queries.shape[0], w, p, k, mode,
                                out), "lbimp_autotune")
     return {name: int(out[i]) for i, name in enumerate(TUNE_KNOBS)}
+
+
+def lbimp_ctx_copy_tuning(dst: Ctx, src: Ctx):
+    _check(_lib.lbimp_ctx_copy_tuning(dst.h, src.h), "lbimp_ctx_copy_tuning")

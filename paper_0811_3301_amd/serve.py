@@ -156,6 +156,23 @@ class GpuExecutor:
                 dist_h=torch.empty((max_batch, kmax), dtype=torch.float32, pin_memory=True),
                 event=torch.cuda.Event()))
 
+    def pretune(self, sample, sizes=(8, 16, 32, 64, 128, 256, 512)):
+        """Autotune the batch shapes the loop will meet -- each (database, band, k) of `sample`
+        at each batch size in `sizes` -- on slot 0, then share the choices with every slot."""
+        torch, L = self.torch, self.L
+        s0 = self.slots[0]
+        shapes = {}
+        for r in sample:
+            shapes.setdefault((r.db, r.w, r.k), []).append(r.y)
+        with torch.cuda.stream(s0.stream):
+            for (db, w, k), ys in sorted(shapes.items()):
+                for q in sizes:
+                    Y = torch.from_numpy(np.stack([ys[i % len(ys)] for i in range(q)]).astype(np.float32)).cuda()
+                    L.lbimp_autotune(s0.ctx, self.dbs[db], Y, w, self.p, k, self.mode)
+        for s in self.slots[1:]:
+            L.lbimp_ctx_copy_tuning(s.ctx, s0.ctx)
+        torch.cuda.synchronize()
+
     def need(self, slot: int, reqs) -> int:
         """Largest workspace among the batch's per-k searches on this slot."""
         ctx = self.slots[slot].ctx
