@@ -187,6 +187,37 @@ def ragged_bench(L, steps, warmup):
                 dtw_fraction=float(st[:, 4].sum() / st[:, 0].sum()))
 
 
+def shape_bench(L, steps):
+    """Shape-like signatures: 50,000 x 512 database, 512 queries, w = 26 and 51, p = 1, 1-NN;
+    two-pass, LB_Keogh-only and brute-force search, autotuned on an untimed first call."""
+    import torch
+    from paper_0811_3301_amd import gen
+    db64, qs64 = gen.make_workload("shape512")
+    N, n = db64.shape
+    Q = qs64.shape[0]
+    ctx = L.Ctx(0)
+    L.lbimp_ctx_set_option(ctx, "autotune", 1)
+    db = L.Db(ctx, torch.from_numpy(db64.astype(np.float32)).cuda())
+    Yd = torch.from_numpy(qs64.astype(np.float32)).cuda()
+    del db64
+    out = dict(workload="shape-like centroid-distance signatures, n=512, database 50000, 512 queries, p=1, 1-NN",
+               N=N, n=n, Q=Q)
+    for w in (26, 51):
+        r = {}
+        for mode, k in (("improved", steps), ("keogh", steps), ("brute", 2)):
+            t = time_mode(L, ctx, db, Yd, w, 1, mode, k, 1)
+            r[mode] = dict(qps=Q / (t["ms_per_step"] / 1e3), ms_per_step=t["ms_per_step"])
+        _, _, st = L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, "improved")
+        r["pruned_keogh"] = float(st[:, 2].sum() / (N * Q))
+        r["pruned_improved"] = float(st[:, 3].sum() / (N * Q))
+        r["dtw_fraction"] = float(st[:, 4].sum() / (N * Q))
+        out[f"w{w}"] = r
+    torch.cuda.synchronize()
+    db.close()
+    ctx.close()
+    return out
+
+
 def serving_bench(L, rates, seconds, max_batch=512, slots=4, budget=16 << 30):
     """Serving: Poisson arrivals over a resident 1,000,000 x 128 random-walk database (512 MB)
     and a 200,000 x 256 side database (20% of requests), w = round(0.1 n), k uniform over
@@ -237,9 +268,10 @@ def main():
     ap.add_argument("--quick", action="store_true", help="two-pass mode only (for profiling runs)")
     ap.add_argument("--no-ragged", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-shapes", action="store_true", help="skip the shape-signature measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
-    ap.add_argument("--only", choices=("ragged", "serving"),
+    ap.add_argument("--only", choices=("ragged", "serving", "shapes"),
                     help="run only the uneven-batch or the serving measurement and print its JSON (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -262,6 +294,9 @@ def main():
     L.load()
     if args.only == "ragged":
         print(json.dumps(ragged_bench(L, args.steps, args.warmup)), flush=True)
+        return
+    if args.only == "shapes":
+        print(json.dumps(shape_bench(L, args.steps)), flush=True)
         return
     if args.only == "serving":
         print(json.dumps(serving_bench(L, rates=(10_000,), seconds=0.3)), flush=True)
@@ -324,6 +359,11 @@ def main():
         log("uneven batch (4096 queries of mixed lengths and bands)")
         ragged = ragged_bench(L, max(3, args.steps // 4), 2)
 
+    shapes = None
+    if not (args.quick or args.no_shapes):
+        log("shape signatures (n=512, w=26 and 51)")
+        shapes = shape_bench(L, max(3, args.steps // 4))
+
     serving = None
     if not (args.quick or args.no_serving):
         log("serving loop")
@@ -362,6 +402,7 @@ def main():
         "lb_single_query_hbm": lbg,
         "batch_latency_ms": dict(p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99))),
         "ragged": ragged,
+        "shapes": shapes,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

@@ -62,6 +62,15 @@ __device__ __forceinline__ void strip_cols4(float (&R)[C], const float (&X)[C], 
     }
 }
 
+// The rows of R computed so far must exist here: the left phase stores only +inf to the ring
+// (its last row lies below the band), so without this use the compiler sinks the arithmetic of
+// every left group past the loads of the later ones and keeps all of them live at once.
+template <int C, int ROWS>
+__device__ __forceinline__ void pin_rows(const float (&R)[C]) {
+#pragma unroll
+    for (int r = 0; r < (ROWS < C ? ROWS : C); ++r) asm volatile("" ::"v"(R[r]));
+}
+
 // One middle column (every row in the band).
 template <int P, int C>
 __device__ __forceinline__ float strip_col1(float (&R)[C], const float (&X)[C], float y, float tc, float tprev) {
@@ -79,8 +88,11 @@ __device__ __forceinline__ float strip_col1(float (&R)[C], const float (&X)[C], 
     return R[C - 1];
 }
 
+// Four waves per SIMD need at most 128 VGPRs: the plain variant is held to that (the few values
+// that do not fit are per-item setup, spilled outside the column loops).  The variant with the
+// LB_Keogh-tail bound keeps U, L reads and its sums and stays at three.
 template <int P, int C, bool CASCADE>
-__global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__restrict__ ring_base, int rb_log2) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CASCADE ? 3 : 4, 8))) void k_dtw_strip(DtwArgs a, int w, float *__restrict__ ring_base, int rb_log2) {
     extern __shared__ float ypad[];  // ypad[j + w + 4] = y[j] for 0 <= j < n, -inf elsewhere; then U, L
     const int lane = threadIdx.x;
     const int n = a.n;
@@ -90,7 +102,10 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
     constexpr bool cascade = CASCADE;  // a.S1 is set exactly for this instantiation
     const float shrink = cascade_shrink(n);
     const int rmask = (1 << rb_log2) - 1;
-    float *ring = ring_base + ((size_t)blockIdx.x << rb_log2) * 64 + lane;  // slot j at ring[(j & rmask) * 64]
+    // this wave's ring (a uniform base); slot j of lane l at ring[(j & rmask) * 64 + l], indexed
+    // with 32-bit offsets so each access needs one offset register
+    float *ring = ring_base + ((size_t)blockIdx.x << rb_log2) * 64;
+    auto rslot = [&](int j) { return (unsigned)(((j & rmask) << 6) | lane); };
     const int S = (n + C - 1) / C;
     const int I00 = n - S * C;  // first row of the first strip (<= 0)
     int64_t cur_q = -1;
@@ -135,7 +150,7 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
             const u64 th = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // the row above the strip, D(I0-1, j), lies in the ring for 0 <= j <= jread
             const int jread = s > 0 ? min(n - 1, I0 - 1 + w) : -1;
-            auto above = [&](int j) { return (j >= 0 && j <= jread) ? ring[(j & rmask) * 64] : kInf; };
+            auto above = [&](int j) { return (j >= 0 && j <= jread) ? ring[rslot(j)] : kInf; };
             float cmin = kInf;
             int jn = INT_MIN;  // columns [jn, jn+4) are prefetched in tn
             float tn[4];
@@ -147,7 +162,7 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
             auto finish4 = [&](int j, const float (&out)[4], bool track) {
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    ring[((j + t) & rmask) * 64] = out[t];
+                    ring[rslot(j + t)] = out[t];
                     if (track) cmin = fminf(cmin, out[t]);
                 }
             };
@@ -170,6 +185,7 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
         }                                                                   \
         fetch(j + 4);                                                       \
         strip_cols4<P, C, kLeft, 4 * (G)>(R, X, yv, tc, tprev, out);        \
+        pin_rows<C, 4 * (G) + 4>(R);                                        \
         finish4(j, out, 4 * (G) + 4 == C);                                  \
         tprev = tc[3];                                                      \
         j += 4;                                                             \
@@ -185,7 +201,7 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
             for (; (jr - j) & 3; ++j) {
                 const float tc1 = above(j);
                 const float o = strip_col1<P, C>(R, X, ypad[yoff + j], tc1, tprev);
-                ring[(j & rmask) * 64] = o;
+                ring[rslot(j)] = o;
                 cmin = fminf(cmin, o);
                 if (j == n - 1) fin = o;
                 tprev = tc1;
@@ -201,7 +217,10 @@ __global__ __launch_bounds__(64) void k_dtw_strip(DtwArgs a, int w, float *__res
                 fetch(j + 4);
                 strip_cols4<P, C, kMid, 0>(R, X, yv, tc, tprev, out);
                 finish4(j, out, true);
-                if (j <= n - 1 && n - 1 < j + 4) fin = out[n - 1 - j];
+                if (j <= n - 1 && n - 1 < j + 4) {  // select, not an indexed (scratch) array
+                    const int o = n - 1 - j;
+                    fin = o == 0 ? out[0] : o == 1 ? out[1] : o == 2 ? out[2] : out[3];
+                }
                 tprev = tc[3];
             }
             // right phase: C columns, column u holds rows u..C-1

@@ -23,6 +23,7 @@ Seeds follow ``SeedSequence([8113301, config_id, role, *extra])``, role 0 = data
 from __future__ import annotations
 
 import numpy as np
+from scipy.ndimage import convolve1d
 
 BASE_SEED = 8113301
 
@@ -51,50 +52,66 @@ def white_noise(count: int, n: int, gen: np.random.Generator) -> np.ndarray:
     return gen.standard_normal((count, n))
 
 
-def _polygon_signature(n: int, gen: np.random.Generator, sigma: float) -> np.ndarray:
-    v = int(gen.integers(5, 13))                      # 5..12 vertices
-    theta = np.sort(gen.uniform(0.0, 2.0 * np.pi, v))
-    r = gen.uniform(0.5, 1.5, v)
-    px, py = r * np.cos(theta), r * np.sin(theta)
-    # area centroid of the closed polygon (shoelace formula)
-    qx, qy = np.roll(px, -1), np.roll(py, -1)
-    cross = px * qy - qx * py
-    area = 0.5 * cross.sum()
-    if abs(area) < 1e-12:
-        cx, cy = px.mean(), py.mean()
-    else:
-        cx = ((px + qx) * cross).sum() / (6.0 * area)
-        cy = ((py + qy) * cross).sum() / (6.0 * area)
-    # n boundary points spaced uniformly in arc length, starting at vertex 0
-    seg = np.hypot(qx - px, qy - py)
-    cum = np.concatenate([[0.0], np.cumsum(seg)])
-    s = np.arange(n) * (cum[-1] / n)
-    k = np.clip(np.searchsorted(cum, s, side="right") - 1, 0, v - 1)
-    t = (s - cum[k]) / np.where(seg[k] > 0, seg[k], 1.0)
-    bx = px[k] + t * (qx[k] - px[k])
-    by = py[k] + t * (qy[k] - py[k])
-    sig = np.hypot(bx - cx, by - cy)
-    # circular Gaussian smoothing (wrap-around), sigma in samples
-    if sigma > 0:
+def _outlines(n: int, v: np.ndarray, theta: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """Distance to the area centroid of n boundary points of each star-shaped polygon (v[c]
+    vertices at sorted angles theta[c, :v[c]] and radii r[c, :v[c]]), spaced uniformly in arc
+    length from vertex 0."""
+    count, V = theta.shape
+    i = np.arange(V)[None, :]
+    live = i < v[:, None]
+    nxt = np.where(i + 1 < v[:, None], i + 1, 0)
+    px = np.where(live, r * np.cos(theta), 0.0)
+    py = np.where(live, r * np.sin(theta), 0.0)
+    qx = np.take_along_axis(px, nxt, axis=1)
+    qy = np.take_along_axis(py, nxt, axis=1)
+    cross = np.where(live, px * qy - qx * py, 0.0)
+    area = 0.5 * cross.sum(axis=1)
+    tiny = np.abs(area) < 1e-12
+    safe = np.where(tiny, 1.0, area)
+    cx = np.where(tiny, px.sum(axis=1) / v, ((px + qx) * cross).sum(axis=1) / (6.0 * safe))
+    cy = np.where(tiny, py.sum(axis=1) / v, ((py + qy) * cross).sum(axis=1) / (6.0 * safe))
+    seg = np.where(live, np.hypot(qx - px, qy - py), 0.0)
+    cum = np.concatenate([np.zeros((count, 1)), np.cumsum(seg, axis=1)], axis=1)   # [count][V+1]
+    s = np.arange(n)[None, :] * (cum[:, -1:] / n)                                    # [count][n]
+    k = (cum[:, None, 1:] <= s[:, :, None]).sum(axis=2)                              # segment of each point
+    k = np.minimum(k, v[:, None] - 1)
+    segk = np.take_along_axis(seg, k, axis=1)
+    t = (s - np.take_along_axis(cum, k, axis=1)) / np.where(segk > 0, segk, 1.0)
+    pxk, pyk = np.take_along_axis(px, k, axis=1), np.take_along_axis(py, k, axis=1)
+    bx = pxk + t * (np.take_along_axis(qx, k, axis=1) - pxk)
+    by = pyk + t * (np.take_along_axis(qy, k, axis=1) - pyk)
+    return np.hypot(bx - cx[:, None], by - cy[:, None])
+
+
+def shape_signatures(count: int, n: int, gen: np.random.Generator, sigma: float = 4.0) -> np.ndarray:
+    """``count`` z-normalised centroid-distance signatures of random star-shaped polygons:
+    5..12 vertices at sorted uniform angles with radii U(0.5, 1.5); the distance of the
+    outline to the area centroid (shoelace formula) at n points spaced uniformly in arc
+    length, circularly smoothed by a Gaussian of ``sigma`` samples, then rotated by a random
+    shift.  Draws, for all series at once: vertex counts, 12 angles and 12 radii per series
+    (the first v used), shifts."""
+    V = 12
+    v = gen.integers(5, 13, count)                                  # 5..12 vertices
+    theta = np.sort(np.where(np.arange(V)[None, :] < v[:, None],
+                             gen.uniform(0.0, 2.0 * np.pi, (count, V)), np.inf), axis=1)
+    theta = np.where(np.isfinite(theta), theta, 0.0)
+    r = gen.uniform(0.5, 1.5, (count, V))
+    shift = gen.integers(0, n, count)
+    sig = np.empty((count, n))
+    for c0 in range(0, count, 2048):
+        c1 = min(count, c0 + 2048)
+        sig[c0:c1] = _outlines(n, v[c0:c1], theta[c0:c1], r[c0:c1])
+    if sigma > 0:  # circular Gaussian smoothing (wrap-around)
         half = int(np.ceil(4 * sigma))
         taps = np.arange(-half, half + 1)
         kern = np.exp(-0.5 * (taps / sigma) ** 2)
         kern /= kern.sum()
-        sm = np.zeros(n)
-        for tap, wgt in zip(taps, kern):
-            sm += wgt * np.roll(sig, tap)
-        sig = sm
-    sig = np.roll(sig, int(gen.integers(0, n)))
-    sd = sig.std()
-    return (sig - sig.mean()) / (sd if sd > 0 else 1.0)
-
-
-def shape_signatures(count: int, n: int, gen: np.random.Generator, sigma: float = 4.0) -> np.ndarray:
-    """``count`` z-normalised centroid-distance signatures of random star-shaped polygons."""
-    out = np.empty((count, n), dtype=np.float64)
-    for c in range(count):
-        out[c] = _polygon_signature(n, gen, sigma)
-    return out
+        sig = convolve1d(sig, kern, axis=1, mode="wrap")
+    cols = (np.arange(n)[None, :] - shift[:, None]) % n   # rotate row c right by shift[c]
+    sig = np.take_along_axis(sig, cols, axis=1)
+    mean = sig.mean(axis=1, keepdims=True)
+    sd = sig.std(axis=1, keepdims=True)
+    return (sig - mean) / np.where(sd > 0, sd, 1.0)
 
 
 def poisson_arrivals(rate_qps: float, count: int, gen: np.random.Generator) -> np.ndarray:

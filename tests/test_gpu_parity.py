@@ -327,6 +327,36 @@ def test_nn_search_rw256_full_size_sampled(L, ctx, p):
     db.close()
 
 
+@pytest.fixture(scope="module")
+def shape512(L, ctx):
+    db64, qs64 = gen.make_workload("shape512")
+    X, Ys = f32(db64), f32(qs64)
+    db = L.Db(ctx, to_dev(X))
+    yield X, Ys, db
+    torch.cuda.synchronize()
+    db.close()
+
+
+@pytest.mark.parametrize("w", [26, 51])
+def test_nn_search_shape512_full_size_sampled(L, ctx, shape512, w):
+    """Shape-like signatures (50,000 x 512, 512 queries, w = 26 and 51, p = 1): the three modes
+    agree on every query, bit for bit, and sampled queries match the oracle."""
+    _say(f"nn_search shape512 full size w={w}")
+    X, Ys, db = shape512
+    Yd = to_dev(Ys)
+    res = {m: L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, m) for m in ("improved", "keogh", "brute")}
+    idx = {m: r[0].cpu().numpy()[:, 0] for m, r in res.items()}
+    dist = {m: r[1].cpu().numpy()[:, 0] for m, r in res.items()}
+    assert np.array_equal(idx["improved"], idx["keogh"]) and np.array_equal(idx["improved"], idx["brute"])
+    assert np.array_equal(dist["improved"].view(np.uint32), dist["brute"].view(np.uint32))
+    sample = [3, 200, 511]
+    check_knn(X.astype(np.float64), Ys[sample].astype(np.float64), w, 1, 1, idx["improved"][sample, None],
+              dist["improved"][sample, None], f"shape512 w={w}")
+    st = res["improved"][2]
+    assert np.all(st[:, 0] == 50_000)
+    assert st[:, 3].sum() > 0  # LB_Improved prunes past LB_Keogh
+
+
 @pytest.mark.parametrize("shape", [2, 3, 4, 5])
 def test_nn_search_sweep_shapes(L, ctx, shape):
     _say(f"nn_search sweep shape {shape}")
