@@ -183,11 +183,17 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
     for (int c0 = 0; c0 < n4; c0 += ICH) {
         const int len = min(ICH, n4 - c0);
         __syncthreads();
+        // Staged rotated: element k of L sits in component k+1 and of U in k+3 (mod 4).  The
+        // register quads of x, L and U start at even registers, so the three operands of each
+        // med3 (x, L, U of element k) then fall in three different VGPR banks (a med3 reading
+        // one bank three times issues slower).  med3 is symmetric, so the result is unchanged.
         for (int t = threadIdx.x; t < QG * ICH; t += 256) {
             int qq = t / ICH, ii = t % ICH;
             if (ii < len) {
-                sU[qq][ii] = Ue[(q0 + qq) * ld4 + c0 + ii];
-                sL[qq][ii] = Le[(q0 + qq) * ld4 + c0 + ii];
+                const float4 u = Ue[(q0 + qq) * ld4 + c0 + ii];
+                const float4 l = Le[(q0 + qq) * ld4 + c0 + ii];
+                sU[qq][ii] = make_float4(u.y, u.z, u.w, u.x);
+                sL[qq][ii] = make_float4(l.w, l.x, l.y, l.z);
             }
         }
         __syncthreads();
@@ -201,10 +207,10 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
 #pragma unroll
                 for (int b = 0; b < CPL; ++b) {
                     float r = acc[a][b];
-                    r = lb_term<P>(r, xv[b].x, l.x, u.x);
-                    r = lb_term<P>(r, xv[b].y, l.y, u.y);
-                    r = lb_term<P>(r, xv[b].z, l.z, u.z);
-                    r = lb_term<P>(r, xv[b].w, l.w, u.w);
+                    r = lb_term<P>(r, xv[b].x, l.y, u.w);
+                    r = lb_term<P>(r, xv[b].y, l.z, u.x);
+                    r = lb_term<P>(r, xv[b].z, l.w, u.y);
+                    r = lb_term<P>(r, xv[b].w, l.x, u.z);
                     acc[a][b] = r;
                 }
             }
