@@ -172,7 +172,8 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
  * choices that change speed and never results -- the number of seeding DTWs, the LB_Keogh
  * sweep tiling, a lane or a group of lanes per pair for the seeding and for the survivors'
  * DTW, pipelined LB_Improved loads -- timing each with HIP events on the context's stream
- * (one choice at a time from the best so far), and keeps the fastest for every later batch
+ * (one choice at a time from the best so far; a choice's time is the best of three timings
+ * of two searches, after one untimed search), and keeps the fastest for every later batch
  * of the same shape (database size and length, effective band, p, k, mode, and Q rounded up
  * to a power of two) in lbimp_nn_search and lbimp_nn_search_ragged.  With the context option
  * "autotune" set, those calls tune a shape they meet for the first time by themselves.
