@@ -179,3 +179,43 @@ def test_ragged_invalid_arguments(L, ctx, dbs):
         L.lbimp_nn_search_ragged(ctx, handles, y, np.array([0, 64]), np.array([0]), -1, 1, 1, "improved")
     with pytest.raises(L.LbimpError):  # k out of range
         L.lbimp_nn_search_ragged(ctx, handles, y, np.array([0, 64]), np.array([0]), 3, 1, 65, "improved")
+
+
+def test_ragged_uneven4096_full_size(L):
+    """The uneven batch the benchmark times -- 4,096 random-walk queries, n uniform over
+    {64, 128, 256, 512, 1024}, w = round(f n) with f in {0.05, 0.1, 0.2}, 20,000 series per
+    length, p = 1, 1-NN -- in its launch configuration (autotuned context, graph replay on four
+    streams): every query equals the search of its group alone, bit for bit, and the first query
+    of every (length, band) group matches the oracle."""
+    _say("ragged uneven batch, full size (4096 queries, 5 x 20000 series)")
+    ctx2 = L.Ctx(0)
+    L.lbimp_ctx_set_option(ctx2, "autotune", 1)
+    dbs64, qs, db_of, w = gen.make_ragged_workload()
+    Xs = [f32(d) for d in dbs64]
+    del dbs64
+    handles = [L.Db(ctx2, to_dev(X)) for X in Xs]
+    try:
+        offsets = np.zeros(len(qs) + 1, np.int64)
+        offsets[1:] = np.cumsum([len(y) for y in qs])
+        packed = to_dev(f32(np.concatenate(qs)))
+        L.lbimp_nn_search_ragged(ctx2, handles, packed, offsets, db_of, w, 1, 1, "improved")  # tunes, captures
+        idx, dist, st = L.lbimp_nn_search_ragged(ctx2, handles, packed, offsets, db_of, w, 1, 1, "improved")
+        idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+        Ys = [f32(y) for y in qs]
+        ai, ad, ast = _alone(L, ctx2, handles, db_of, w, Ys, 1, 1, "improved", list(gen.RAGGED_LENGTHS))
+        assert np.array_equal(idx, ai)
+        assert np.array_equal(dist.view(np.uint32), ad.view(np.uint32))
+        assert np.array_equal(st[:, :5], ast[:, :5])
+        assert np.all(st[:, 0] == 20_000)
+        groups = sorted({(int(b), int(wq)) for b, wq in zip(db_of, w)})
+        assert len(groups) == 15
+        for b, wq in groups:
+            q = next(q for q in range(len(qs)) if db_of[q] == b and w[q] == wq)
+            _say(f"  oracle check n={gen.RAGGED_LENGTHS[b]} w={wq} q={q}")
+            check_knn(Xs[b].astype(np.float64), Ys[q].astype(np.float64)[None, :], wq, 1, 1, idx[q:q + 1],
+                      dist[q:q + 1], f"uneven4096 q={q}")
+    finally:
+        torch.cuda.synchronize()
+        for h in handles:
+            h.close()
+        ctx2.close()

@@ -77,3 +77,41 @@ def test_serving_batches_overlap_under_load(L, ctx, workload):
     done = np.array([b[1] for b in batches])
     # some batch was admitted before an earlier-admitted batch had finished (overlap)
     assert np.any(admit[1:] < np.maximum.accumulate(done)[:-1])
+
+
+def test_serving_full_size_sampled(L, ctx):
+    """The serving workload the benchmark runs -- a resident 1,000,000 x 128 random-walk database
+    (512 MB) and a 200,000 x 256 side database, w = round(0.1 n), k in {1, 5, 10} -- at 20k q/s
+    offered, with the benchmark's four slots, batches of at most 512 and a 16 GiB budget, after
+    pretuning: every result equals the same query searched alone, bit for bit, and the first
+    request of each database matches the oracle."""
+    _say("serving full size: 1M x 128 and 200k x 256 databases, 400 requests at 20k q/s")
+    dbs64, req = gen.make_serving_workload(20_000, 400)
+    Xs = [f32(d) for d in dbs64]
+    del dbs64
+    handles = [L.Db(ctx, to_dev(X)) for X in Xs]
+    reqs = [Request(rid=i, t_arrive=float(req["t"][i]), db=int(req["db"][i]), y=f32(req["y"][i]),
+                    w=int(req["w"][i]), k=int(req["k"][i])) for i in range(len(req["t"]))]
+    ex = GpuExecutor(handles, slots=4, max_batch=512, kmax=10)
+    try:
+        ex.pretune(reqs[:200])
+        results, summary = serve(reqs, ex, budget_bytes=16 << 30, max_batch=512)
+    finally:
+        ex.close()
+    try:
+        got = {r.rid: r for r in results}
+        assert len(got) == len(reqs) and summary["p99_ms"] >= summary["p50_ms"] > 0
+        for r in reqs:
+            ai, ad = _alone(L, ctx, handles, r)
+            assert np.array_equal(got[r.rid].idx, ai), r.rid
+            assert np.array_equal(got[r.rid].dist.view(np.uint32), ad.view(np.uint32)), r.rid
+        for db in (0, 1):
+            r = next(r for r in reqs if r.db == db)
+            _say(f"  oracle check db={db} rid={r.rid} k={r.k}")
+            res = got[r.rid]
+            check_knn(Xs[db].astype(np.float64), r.y.astype(np.float64)[None, :], r.w, 1, r.k, res.idx[None, :],
+                      res.dist[None, :], f"served full-size rid={r.rid}")
+    finally:
+        torch.cuda.synchronize()
+        for h in handles:
+            h.close()
