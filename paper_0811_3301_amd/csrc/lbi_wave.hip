@@ -127,13 +127,16 @@ template <int P, int M>
 __global__ __launch_bounds__(64) void k_lbi_wave(LbiArgs a, int w) {
     extern __shared__ float sm[];
     float *sg = sm, *sh = sm + 64 * M;  // [M][64] each
+    // This lane's slice of the query envelope, [M][64] each: kept in LDS rather than registers
+    // (each lane reads only its own column), which leaves room for a second wave per SIMD.
+    float *sUq = sm + 2 * 64 * M, *sLq = sm + 3 * 64 * M;
     const int lane = threadIdx.x;
     const int n = a.n;
     const int K = 2 * w + 1;
     const int p0 = lane * M;
     const int rj = min(M, (p0 + K - 1) / K * K - p0);  // offset of the block start in this lane (M: none)
     int64_t cur_q = -1;
-    float Uv[M], Lv[M], yv[M];
+    float yv[M];
     int64_t q;
     long long b;
     ItemCursor items(a.pl, a.prefix, a.Q, 64);
@@ -143,8 +146,8 @@ __global__ __launch_bounds__(64) void k_lbi_wave(LbiArgs a, int w) {
 #pragma unroll
             for (int j = 0; j < M; ++j) {
                 const int i = min(p0 + j, n - 1);
-                Uv[j] = Uq[i];
-                Lv[j] = Lq[i];
+                sUq[j * 64 + lane] = Uq[i];
+                sLq[j * 64 + lane] = Lq[i];
                 yv[j] = yq[i];
             }
             cur_q = q;
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(64) void k_lbi_wave(LbiArgs a, int w) {
         for (int t = 0; t < cnt; ++t) {
             float xp[M];
 #pragma unroll
-            for (int j = 0; j < M; ++j) xp[j] = __builtin_amdgcn_fmed3f(xr[j], Lv[j], Uv[j]);
+            for (int j = 0; j < M; ++j) xp[j] = __builtin_amdgcn_fmed3f(xr[j], sLq[j * 64 + lane], sUq[j * 64 + lane]);
             if (t + 1 < cnt) load_row(t + 1);
             float acc = lbi_pass<P, M, true>(xp, yv, sg, sh, w, n, lane, rj);
             acc += lbi_pass<P, M, false>(xp, yv, sg, sh, w, n, lane, rj);
@@ -204,7 +207,7 @@ bool lbi_wave_supported(int n, int w) {
 
 template <int P, int M>
 static void lbi_wave_launch(int w, int num_cu, const LbiArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float) * 2 * 64 * (size_t)M;
+    const size_t lds = sizeof(float) * 4 * 64 * (size_t)M;
     hipLaunchKernelGGL((k_lbi_wave<P, M>), dim3(persistent_grid(k_lbi_wave<P, M>, lds, num_cu)), dim3(64), lds, s, a,
                        w);
 }
