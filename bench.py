@@ -367,7 +367,7 @@ def main():
     serving = None
     if not (args.quick or args.no_serving):
         log("serving loop")
-        serving = serving_bench(L, rates=(1_000, 10_000, 20_000, 35_000, 50_000), seconds=0.5)
+        serving = serving_bench(L, rates=(1_000, 2_000, 5_000, 10_000, 20_000, 35_000, 50_000), seconds=0.5)
 
     cpu = None
     if not args.no_cpu:
