@@ -266,6 +266,40 @@ def test_nn_search_ties_constant_and_negative(L, ctx, mode):
     db.close()
 
 
+@pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
+@pytest.mark.parametrize("n,w", [(96, 9), (200, 80)])
+@pytest.mark.parametrize("k", [10, 64])
+def test_nn_search_large_k(L, ctx, mode, n, w, k):
+    """k up to the maximum of 64 (the k-th best key as the threshold, sorted output), in the
+    lane-per-pair and the strip DTW paths, against the oracle."""
+    _say(f"nn_search large k={k} n={n} w={w} mode={mode}")
+    X = walks(1500, n, 41)
+    Ys = walks(6, n, 42)
+    db = L.Db(ctx, to_dev(X))
+    for p in (1, 2):
+        idx, dist, st = L.lbimp_nn_search(ctx, db, to_dev(Ys), w, p, k, mode)
+        idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+        check_knn(X, Ys, w, p, k, idx, dist, f"large k={k} {mode} p={p}")
+        assert np.all(np.diff(dist, axis=1) >= 0)
+        check_stats(X, Ys, w, p, st, mode)
+    db.close()
+
+
+@pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
+def test_nn_search_k64_ties_in_index_order(L, ctx, mode):
+    """Seventy exact copies of one series: the 64 nearest neighbours of that series are the 64
+    smallest indices among the copies, in index order, all at distance 0."""
+    _say(f"nn_search k=64 ties mode={mode}")
+    X = walks(400, 64, 43)
+    copies = np.sort(np.random.default_rng(44).choice(400, 70, replace=False))
+    X[copies] = X[copies[0]]
+    db = L.Db(ctx, to_dev(X))
+    idx, dist, _ = L.lbimp_nn_search(ctx, db, to_dev(X[copies[:1]]), 6, 1, 64, mode)
+    assert list(idx.cpu().numpy()[0]) == list(copies[:64])
+    assert np.all(dist.cpu().numpy()[0] == 0)
+    db.close()
+
+
 def test_nn_search_empty_database_and_k_above_n(L, ctx):
     _say("nn_search empty database, k > N")
     Ys = walks(3, 20, 13)
