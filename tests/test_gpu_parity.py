@@ -228,6 +228,7 @@ EDGE_CASES = {
     "w_ge_n": dict(N=100, n=30, w=30),
     "wide_wave_path": dict(N=150, n=256, w=80),
     "ragged_n": dict(N=200, n=131, w=13),
+    "long_wide": dict(N=80, n=2300, w=600),  # generic LB_Improved, strip DTW, LDS seeding DTW
 }
 
 
