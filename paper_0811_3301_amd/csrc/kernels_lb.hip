@@ -159,13 +159,21 @@ template <int P, int QG, int CPL, bool ROOT>
 __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il, int64_t T, int64_t N, int n4,
                                                     const float4 *__restrict__ Ue, const float4 *__restrict__ Le,
                                                     int ld4, int64_t Q, float *__restrict__ out, int64_t ldo,
-                                                    bool pad_inf, unsigned long long *__restrict__ wmin, int64_t ldw) {
+                                                    bool pad_inf, unsigned long long *__restrict__ wmin, int64_t ldw,
+                                                    unsigned gx, unsigned gy) {
     constexpr int ICH = 32;
     __shared__ float4 sU[QG][ICH];
     __shared__ float4 sL[QG][ICH];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wave) * CPL;
-    const int64_t q0 = (int64_t)blockIdx.y * QG;
+    // One-dimensional grid of gx (candidate tile groups) x gy (query groups) blocks.  Blocks
+    // are dealt to the 8 XCDs in turn (block b on XCD b % 8); renumbering them so that logical
+    // neighbours share an XCD, with query groups fastest, runs the query groups of one tile
+    // group back to back on one XCD, where its L2 serves the tile to all of them.
+    const unsigned nb = gx * gy, per = nb / 8, b = blockIdx.x;
+    const unsigned lid = b < per * 8 ? (b % 8) * per + b / 8 : b;
+    const unsigned bx = lid / gy, by = lid % gy;
+    const int64_t tile0 = ((int64_t)bx * 4 + wave) * CPL;
+    const int64_t q0 = (int64_t)by * QG;
     float acc[QG][CPL];
 #pragma unroll
     for (int a = 0; a < QG; ++a)
@@ -218,7 +226,7 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
     }
     if (wmin) {
         // smallest (value, index) key of this wave's candidates, per query: seed candidates
-        const int64_t wid = (int64_t)blockIdx.x * 4 + wave;
+        const int64_t wid = (int64_t)bx * 4 + wave;
 #pragma unroll
         for (int a = 0; a < QG; ++a) {
             unsigned long long k = kNoKey;
@@ -261,9 +269,9 @@ static hipError_t sweep_variant(const float4 *il, int64_t N, int n4, const float
                                 int64_t Q, float *out, int64_t ldo, bool pad_inf, unsigned long long *wmin,
                                 hipStream_t s) {
     int64_t T = (N + 63) / 64;
-    dim3 grid((unsigned)((T + 4 * CPL - 1) / (4 * CPL)), (unsigned)((Q + QG - 1) / QG));
-    hipLaunchKernelGGL((k_lbk_sweep<P, QG, CPL, ROOT>), grid, dim3(256), 0, s, il, T, N, n4, Ue, Le, ld4, Q, out,
-                       ldo, pad_inf, wmin, (int64_t)grid.x * 4);
+    const unsigned gx = (unsigned)((T + 4 * CPL - 1) / (4 * CPL)), gy = (unsigned)((Q + QG - 1) / QG);
+    hipLaunchKernelGGL((k_lbk_sweep<P, QG, CPL, ROOT>), dim3(gx * gy), dim3(256), 0, s, il, T, N, n4, Ue, Le, ld4, Q,
+                       out, ldo, pad_inf, wmin, (int64_t)gx * 4, gx, gy);
     return hipGetLastError();
 }
 
