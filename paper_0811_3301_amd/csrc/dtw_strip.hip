@@ -92,7 +92,8 @@ __device__ __forceinline__ float strip_col1(float (&R)[C], const float (&X)[C], 
 // that do not fit are per-item setup, spilled outside the column loops).  The variant with the
 // LB_Keogh-tail bound keeps U, L reads and its sums and stays at three.
 template <int P, int C, bool CASCADE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CASCADE ? 3 : 4, 8))) void k_dtw_strip(DtwArgs a, int w, float *__restrict__ ring_base, int rb_log2) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(CASCADE ? 3 : 4, 8)))
+void k_dtw_strip(DtwArgs a, int w, float *__restrict__ ring_base, int rb_log2) {
     extern __shared__ float ypad[];  // ypad[j + w + 4] = y[j] for 0 <= j < n, -inf elsewhere; then U, L
     const int lane = threadIdx.x;
     const int n = a.n;

@@ -168,7 +168,8 @@ __global__ __launch_bounds__(64) void k_lbi_wave(LbiArgs a, int w) {
         for (int t = 0; t < cnt; ++t) {
             float xp[M];
 #pragma unroll
-            for (int j = 0; j < M; ++j) xp[j] = __builtin_amdgcn_fmed3f(xr[j], sLq[j * 64 + lane], sUq[j * 64 + lane]);
+            for (int j = 0; j < M; ++j)
+                xp[j] = __builtin_amdgcn_fmed3f(xr[j], sLq[j * 64 + lane], sUq[j * 64 + lane]);
             if (t + 1 < cnt) load_row(t + 1);
             float acc = lbi_pass<P, M, true>(xp, yv, sg, sh, w, n, lane, rj);
             acc += lbi_pass<P, M, false>(xp, yv, sg, sh, w, n, lane, rj);
