@@ -16,7 +16,7 @@ namespace lbimp {
 // +inf on both sides, so columns outside [0, n) cost +inf with no branch; the virtual cell
 // (-1,-1) = 0 is D[W] of row -1.  Per cell: one subtract, one 3-way min, one add (|d|, p = 1)
 // or fma (d*d, p = 2).
-// Early abandoning: every 4 rows the row minimum bounds the result (a path crosses every row
+// Early abandoning: after every group of rows the row minimum bounds the result (a path crosses every row
 // and costs are non-negative); a lane whose (bound, index) key reaches the threshold key can
 // no longer win and stops.  The wave leaves the row loop once every lane has stopped.
 template <int P, int W>
@@ -32,17 +32,19 @@ __device__ __forceinline__ void dtw_row(float (&D)[2 * W + 1], float xi, const f
     }
 }
 
-// Four rows at once in skewed order: step s updates cell k = s - r of row r, rows ascending.
+// R rows at once in skewed order: step s updates cell k = s - r of row r, rows ascending.
 // The in-place reads are unchanged -- when (r, k) runs, D[k] and D[k+1] still hold row r-1
-// and D[k-1] already holds row r -- but the four dependency chains interleave, which hides
-// the latency of the serial left-to-right chain of each row.
-template <int P, int W>
-__device__ __forceinline__ void dtw_rows4(float (&D)[2 * W + 1], const float (&xs)[4], const float *yrow0) {
+// and D[k-1] already holds row r -- but the R dependency chains interleave, which hides the
+// latency of the serial left-to-right chain of each row.  More rows hide more latency, but a
+// band wider than w = 32 at eight rows unrolls past the point where the compiler keeps D in
+// registers (it moves the array to scratch memory), so wide bands take four rows per step.
+template <int P, int W, int R>
+__device__ __forceinline__ void dtw_rowsR(float (&D)[2 * W + 1], const float (&xs)[R], const float *yrow0) {
     constexpr int BW = 2 * W + 1;
 #pragma unroll
-    for (int s = 0; s < BW + 3; ++s) {
+    for (int s = 0; s < BW + R - 1; ++s) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
             const int k = s - r;
             if (k >= 0 && k < BW) {
                 const float d = xs[r] - yrow0[r + k];
@@ -55,13 +57,16 @@ __device__ __forceinline__ void dtw_rows4(float (&D)[2 * W + 1], const float (&x
     }
 }
 
+constexpr int lane_rows(int w) { return w <= 32 ? 8 : 4; }
+
 template <int P, int W, bool CASCADE>
 __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
     constexpr int BW = 2 * W + 1;
+    constexpr int kLaneRows = lane_rows(W);
     extern __shared__ float ypad[];  // ypad[t] = y[t - W], +inf outside [0, n); then U, L when a.S1
     const int lane = threadIdx.x;
     const int n = a.n;
-    const int plen = n + BW + 4;
+    const int plen = n + BW + kLaneRows;
     float *sU = ypad + plen, *sL = sU + n;
     constexpr bool cascade = CASCADE;  // a.S1 is set exactly for this instantiation
     const float shrink = cascade_shrink(n);
@@ -93,33 +98,33 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
 #pragma unroll
         for (int k = 0; k < BW; ++k) D[k] = (k == W) ? 0.f : kInf;
         int stopped = 0;
-        const int nfull = n & ~3;
-        float xs[4];
+        const int nfull = n - n % kLaneRows;
+        float xs[kLaneRows];
         if (nfull > 0) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) xs[r] = x[r];
+            for (int r = 0; r < kLaneRows; ++r) xs[r] = x[r];
         }
         int i0 = 0;
-        // The threshold used after each 4-row group is loaded one group ahead, from one pointer
+        // The threshold used after each group of rows is loaded one group ahead, from one pointer
         // with no branch around the load, so the wait for it lands where it is used.
         const u64 *tq = a.tkeys + q;
         u64 tcur = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         float s1v = 0.f;
         if constexpr (cascade) s1v = a.S1[q * a.ldS + c];
         float done = 0.f;  // LB_Keogh^p terms of the rows already computed
-        for (; i0 < nfull; i0 += 4) {
-            float xn[4];
-            const int inext = i0 + 4 < nfull ? i0 + 4 : i0;  // prefetch the next 4 rows
+        for (; i0 < nfull; i0 += kLaneRows) {
+            float xn[kLaneRows];
+            const int inext = i0 + kLaneRows < nfull ? i0 + kLaneRows : i0;  // prefetch the next rows
 #pragma unroll
-            for (int r = 0; r < 4; ++r) xn[r] = x[inext + r];
+            for (int r = 0; r < kLaneRows; ++r) xn[r] = x[inext + r];
             const u64 tnext = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            dtw_rows4<P, W>(D, xs, ypad + i0);
+            dtw_rowsR<P, W, kLaneRows>(D, xs, ypad + i0);
             if constexpr (cascade) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) done += lbk_term<P>(xs[r], sL[i0 + r], sU[i0 + r]);
+                for (int r = 0; r < kLaneRows; ++r) done += lbk_term<P>(xs[r], sL[i0 + r], sU[i0 + r]);
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) xs[r] = xn[r];
+            for (int r = 0; r < kLaneRows; ++r) xs[r] = xn[r];
             if (a.abandon) {
                 float mn = D[0];
 #pragma unroll
@@ -147,7 +152,7 @@ template <int P, int W>
 static void dtw_lane_launch(int num_cu, const DtwArgs &a_in, hipStream_t s) {
     DtwArgs a = a_in;
     auto lds_of = [&](bool cascade) {
-        return sizeof(float) * ((size_t)a.n + 2 * W + 1 + 4 + (cascade ? 2 * (size_t)a.n : 0));
+        return sizeof(float) * ((size_t)a.n + 2 * W + 1 + lane_rows(W) + (cascade ? 2 * (size_t)a.n : 0));
     };
     if (a.S1 && lds_of(true) > kLdsBudget) a.S1 = nullptr;  // no room for U, L: row minimum only
     const size_t lds = lds_of(a.S1 != nullptr);
