@@ -352,17 +352,31 @@ __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, in
     float *row = S1 + q * ldS;
     unsigned long long top[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
     const int64_t count = FROM_KEYS ? nw : N;
-    for (int64_t c = threadIdx.x; c < count; c += 256) {
-        unsigned long long k = FROM_KEYS ? wmin[q * nw + c]
-                                         : ((unsigned long long)__float_as_uint(row[c]) << 32) | (unsigned long long)c;
-        if (k < top[3]) {
-            top[3] = k;
+    // Thread t takes entries t, t + 256, t + 512, ...; eight of them are loaded before the first
+    // is inserted, so a pass waits for memory once per eight loads.
+    constexpr int U = 8;
+    for (int64_t c0 = threadIdx.x; c0 < count; c0 += 256 * U) {
+        unsigned long long kk[U];
 #pragma unroll
-            for (int a = 3; a > 0; --a) {
-                if (top[a] < top[a - 1]) {
-                    unsigned long long t = top[a];
-                    top[a] = top[a - 1];
-                    top[a - 1] = t;
+        for (int u = 0; u < U; ++u) {
+            const int64_t c = c0 + u * 256;
+            const int64_t cc = c < count ? c : count - 1;
+            const unsigned long long k =
+                FROM_KEYS ? wmin[q * nw + cc] : ((unsigned long long)__float_as_uint(row[cc]) << 32) | (unsigned long long)cc;
+            kk[u] = c < count ? k : kNoKey;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned long long k = kk[u];
+            if (k < top[3]) {
+                top[3] = k;
+#pragma unroll
+                for (int a = 3; a > 0; --a) {
+                    if (top[a] < top[a - 1]) {
+                        unsigned long long t = top[a];
+                        top[a] = top[a - 1];
+                        top[a - 1] = t;
+                    }
                 }
             }
         }
@@ -418,17 +432,22 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, i
     const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64 * CH;
     const unsigned long long t = thr[q];
     const float *row = S1 + q * ldS;
+    // All CH loads are issued before the first test (a load under `c < N` would be a branch of
+    // its own, waited on before its ballot); positions past N read the last value and are
+    // masked out after.
+    float v[CH];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int64_t c = base + ch * 64 + lane;
+        v[ch] = row[c < N ? c : N - 1];
+    }
     unsigned long long masks[CH];
     int total = 0;
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch) {
-        int64_t c = base + ch * 64 + lane;
-        bool keep = false;
-        if (c < N) {
-            unsigned long long k = ((unsigned long long)__float_as_uint(row[c]) << 32) | (unsigned long long)c;
-            keep = k < t;
-        }
-        masks[ch] = __ballot(keep);
+        const int64_t c = base + ch * 64 + lane;
+        const unsigned long long k = ((unsigned long long)__float_as_uint(v[ch]) << 32) | (unsigned long long)c;
+        masks[ch] = __ballot(c < N && k < t);
         total += __popcll(masks[ch]);
     }
     if (lane == 0) wtot[wave] = total;
@@ -465,32 +484,36 @@ hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, co
 // ------------------------------------------------------------------ work-item prefix
 __global__ __launch_bounds__(1024) void k_items_prefix(const int *__restrict__ cnt, int64_t fixed, int64_t Q,
                                                         int batch, long long *__restrict__ prefix) {
-    __shared__ long long part[1024];
-    __shared__ long long carry;
-    if (threadIdx.x == 0) {
-        carry = 0;
-        prefix[0] = 0;
-    }
-    __syncthreads();
+    // Inclusive scan of each wave's 64 item counts by lane shifts, then each wave adds the
+    // totals of the waves before it: two barriers per 1024 queries.
+    __shared__ long long wsum[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) prefix[0] = 0;
+    long long carry = 0;  // items of the queries before this chunk (the same in every thread)
     for (int64_t q0 = 0; q0 < Q; q0 += 1024) {
-        int64_t q = q0 + threadIdx.x;
+        const int64_t q = q0 + threadIdx.x;
         long long v = 0;
         if (q < Q) {
-            long long c = cnt ? (long long)cnt[q] : (long long)fixed;
+            const long long c = cnt ? (long long)cnt[q] : (long long)fixed;
             v = (c + batch - 1) / batch;
         }
-        part[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            long long add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long t = __shfl_up(v, off);
+            if (lane >= off) v += t;
         }
-        if (q < Q) prefix[q + 1] = carry + part[threadIdx.x];
+        if (lane == 63) wsum[wave] = v;
         __syncthreads();
-        if (threadIdx.x == 1023) carry += part[1023];
-        __syncthreads();
+        long long before = carry, chunk = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const long long t = wsum[w];
+            if (w < wave) before += t;
+            chunk += t;
+        }
+        if (q < Q) prefix[q + 1] = before + v;
+        carry += chunk;
+        __syncthreads();  // wsum is rewritten by the next chunk
     }
 }
 

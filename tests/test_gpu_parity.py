@@ -248,6 +248,20 @@ def test_nn_search_edge_cases(L, ctx, case, mode):
 
 
 @pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
+def test_nn_search_many_queries(L, ctx, mode):
+    """2600 queries in one call: the work-item prefix over queries spans three 1024-query chunks."""
+    _say(f"nn_search many queries Q=2600 mode={mode}")
+    X = walks(500, 32, 44)
+    Ys = walks(2600, 32, 45)
+    db = L.Db(ctx, to_dev(X))
+    for p, k in ((1, 1), (2, 3)):
+        idx, dist, st = L.lbimp_nn_search(ctx, db, to_dev(Ys), 3, p, k, mode)
+        check_knn(X, Ys, 3, p, k, idx.cpu().numpy(), dist.cpu().numpy(), f"Q2600 {mode} p={p} k={k}")
+        check_stats(X, Ys, 3, p, st, mode)
+    db.close()
+
+
+@pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
 def test_nn_search_ties_constant_and_negative(L, ctx, mode):
     _say(f"nn_search ties mode={mode}")
     g = np.random.default_rng(21)
