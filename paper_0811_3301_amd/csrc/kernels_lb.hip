@@ -59,13 +59,18 @@ __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, i
     }
     const float *yb = y + b * (int64_t)n;
     float *gmax = sm, *gmin = sm + n, *hmax = sm + 2 * n, *hmin = sm + 3 * n;
+    // The series is first copied into hmin by the whole block (coalesced), so the serial walks
+    // over a block wait on LDS, not on global memory.  The backward walk reads hmin[i] before
+    // it overwrites it, going down, and different threads walk disjoint blocks.
+    for (int i = threadIdx.x; i < n; i += blockDim.x) hmin[i] = yb[i];
+    __syncthreads();
     const int K = 2 * w + 1;
     const int nb = (n + K - 1) / K;
     for (int blk = threadIdx.x; blk < nb; blk += blockDim.x) {
         int s = blk * K, e = min(n, s + K);
         float mx = -kInf, mn = kInf;
         for (int i = s; i < e; ++i) {
-            float v = yb[i];
+            float v = hmin[i];
             mx = fmaxf(mx, v);
             mn = fminf(mn, v);
             gmax[i] = mx;
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, i
         mx = -kInf;
         mn = kInf;
         for (int i = e - 1; i >= s; --i) {
-            float v = yb[i];
+            float v = hmin[i];
             mx = fmaxf(mx, v);
             mn = fminf(mn, v);
             hmax[i] = mx;
