@@ -293,9 +293,8 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     const lbimp_db *db = sp.db;
 
     stage(0);
-    HIPTRY(launch_fill_u64(b.best, kNoKey, Q, s));
-    HIPTRY(launch_fill_u64(b.thr, kNoKey, Q, s));
-    HIPTRY(launch_envelope(sp.queries, Q, d.Qp, n, wb, b.Ue, b.Le, d.ldq, s));
+    // the envelope kernel also resets the best-so-far and threshold keys of the Q queries
+    HIPTRY(launch_envelope(sp.queries, Q, d.Qp, n, wb, b.Ue, b.Le, d.ldq, s, b.best, b.thr));
     stage(1);
     if (d.brute) {
         for (int i = 2; i <= 6; ++i) stage(i);

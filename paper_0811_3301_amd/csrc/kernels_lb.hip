@@ -44,8 +44,15 @@ hipError_t launch_pack(const float *rows, int64_t N, int n, float4 *il, hipStrea
 // the block start, h = running max/min to the block end; the window value is
 // max(h[s], g[e]) across a block boundary, g[e] when s starts its block, h[s] when the
 // window is cut by the series end inside one block.
+// Narrow bands (2w+1 <= kDirectWindow) take the window maximum and minimum of every output
+// directly, one output per thread, from the series in LDS: the plain definition, with no
+// serial walk.  keys0 / keys1 (optional) are set to "no key" for the B real rows, so a search
+// needs no separate fill launches for its best-so-far and threshold keys.
+constexpr int kDirectWindow = 128;
 __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, int64_t B, int n, int w,
-                                                   float *__restrict__ U, float *__restrict__ L, int ldo) {
+                                                   float *__restrict__ U, float *__restrict__ L, int ldo,
+                                                   unsigned long long *__restrict__ keys0,
+                                                   unsigned long long *__restrict__ keys1) {
     extern __shared__ float sm[];
     int64_t b = blockIdx.x;
     float *Ub = U + b * (int64_t)ldo;
@@ -57,14 +64,36 @@ __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, i
         }
         return;
     }
+    if (threadIdx.x == 0) {
+        if (keys0) keys0[b] = kNoKey;
+        if (keys1) keys1[b] = kNoKey;
+    }
     const float *yb = y + b * (int64_t)n;
     float *gmax = sm, *gmin = sm + n, *hmax = sm + 2 * n, *hmin = sm + 3 * n;
-    // The series is first copied into hmin by the whole block (coalesced), so the serial walks
-    // over a block wait on LDS, not on global memory.  The backward walk reads hmin[i] before
-    // it overwrites it, going down, and different threads walk disjoint blocks.
+    // The series is first copied into hmin by the whole block (coalesced), so the reads below
+    // wait on LDS, not on global memory.  The backward walk reads hmin[i] before it overwrites
+    // it, going down, and different threads walk disjoint blocks.
     for (int i = threadIdx.x; i < n; i += blockDim.x) hmin[i] = yb[i];
     __syncthreads();
     const int K = 2 * w + 1;
+    if (K <= kDirectWindow) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int s = max(0, i - w), e = min(n - 1, i + w);
+            float u = -kInf, l = kInf;
+            for (int j = s; j <= e; ++j) {
+                const float v = hmin[j];
+                u = fmaxf(u, v);
+                l = fminf(l, v);
+            }
+            Ub[i] = u;
+            Lb[i] = l;
+        }
+        for (int i = n + threadIdx.x; i < ldo; i += blockDim.x) {
+            Ub[i] = kInf;
+            Lb[i] = -kInf;
+        }
+        return;
+    }
     const int nb = (n + K - 1) / K;
     for (int blk = threadIdx.x; blk < nb; blk += blockDim.x) {
         int s = blk * K, e = min(n, s + K);
@@ -111,10 +140,10 @@ __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, i
 }
 
 hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w, float *U, float *L, int ldo,
-                           hipStream_t s) {
+                           hipStream_t s, unsigned long long *keys0, unsigned long long *keys1) {
     if (Bpad == 0) return hipSuccess;
     size_t lds = sizeof(float) * 4 * (size_t)n;
-    hipLaunchKernelGGL(k_envelope, dim3((unsigned)Bpad), dim3(256), lds, s, y, B, n, w, U, L, ldo);
+    hipLaunchKernelGGL(k_envelope, dim3((unsigned)Bpad), dim3(256), lds, s, y, B, n, w, U, L, ldo, keys0, keys1);
     return hipGetLastError();
 }
 

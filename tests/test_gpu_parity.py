@@ -65,7 +65,8 @@ def walks(count, n, seed):
 
 # ------------------------------------------------------------------ envelopes
 @pytest.mark.parametrize("B,n,w", [(3, 1, 0), (2, 2, 1), (4, 63, 5), (4, 64, 0), (5, 65, 64), (2, 100, 200),
-                                   (3, 257, 26), (2, 1024, 205), (1, 4096, 409)])
+                                   (3, 257, 26), (2, 300, 63), (2, 1024, 205),
+                                   (1, 4096, 409)])
 def test_envelope(L, ctx, B, n, w):
     _say(f"envelope B={B} n={n} w={w}")
     Y = walks(B, n, n + w)
