@@ -298,7 +298,6 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     stage(1);
     if (d.brute) {
         for (int i = 2; i <= 6; ++i) stage(i);
-        HIPTRY(launch_items_prefix(nullptr, N, Q, dtw_batch(n, wb, false), b.prefix, s));
         PairList all{nullptr, 0, nullptr, N};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, all, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
                           k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, nullptr, nullptr, false, false, b.ring,
@@ -313,7 +312,6 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         // Seeds: few pairs per query on the critical path, so a group of lanes per pair (low
         // latency); they run to completion, their DTWs finishing together.
         const bool seed_ll = !sp.kn.seed_lane;
-        HIPTRY(launch_items_prefix(nullptr, d.S, Q, dtw_batch(n, wb, seed_ll), b.prefix, s));
         PairList seedl{b.seeds, d.S, nullptr, d.S};
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, seedl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
                           k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, seed_ll, b.ring,
@@ -861,7 +859,6 @@ int lbimp_lb_improved(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, cons
     HIPTRY(launch_lbk_sweep(p, 0, il, N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4, 1, S1,
                             N, false, false, nullptr, s));
     HIPTRY(launch_fill_i32(ctr, 0, 1, s));
-    HIPTRY(launch_items_prefix(nullptr, N, 1, WL, prefix, s));
     QueryData qd{y, n, U, L, n};
     PairList pl{nullptr, 0, nullptr, N};
     HIPTRY(launch_lbi(p, x, (int64_t)N * n * 4, n, wb, qd, pl, S1, N, prefix, 1, ctr, persistent_grid(ctx), nullptr, nullptr, 0,
@@ -892,7 +889,6 @@ int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, in
     hipStream_t s = ctx->stream;
     HIPTRY(launch_fill_i32(ctr, 0, 1, s));
     HIPTRY(launch_fill_u64(nothr, kNoKey, 1, s));
-    HIPTRY(launch_items_prefix(nullptr, N, 1, dtw_batch(n, wb, ll), prefix, s));
     QueryData qd{y, n, nullptr, nullptr, 0};
     PairList pl{nullptr, 0, nullptr, N};
     // no threshold: nothing is abandoned and nothing appended (out_root receives every distance)

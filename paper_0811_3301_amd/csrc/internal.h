@@ -81,7 +81,8 @@ struct QueryData {
 // Second pass.  S2 = S1[q][c] + sum_i d(y_i, env(H(x_c, y)))^p.  With thr: survivors with
 // key(S2, c) < thr[q] are appended to list2/cnt2.  With out_root: out_root[c] = S2^(1/p)
 // (single query).  prefix: items of `lbi_batch(n, w)` pairs; 0 means the per-lane envelope
-// state of this (n, w) does not fit in LDS.
+// state of this (n, w) does not fit in LDS.  The kernels read prefix (launch_items_prefix
+// over pl.cnt) only when pl.cnt is set; a fixed count per query maps items arithmetically.
 int lbi_batch(int n, int w);
 hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, QueryData qd, PairList pl, const float *S1,
                       int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
@@ -92,7 +93,8 @@ hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, 
 // for early abandoning.  thr/res/rescnt (k > 1): keys below thr[q] are appended to res[q].
 // out_root (single query): out_root[c] = DTW_p.  abandon=false computes every DTW in full.
 // low_latency: a group of lanes per pair (few pairs, each finished quickly) instead of a lane
-// per pair (many pairs, highest throughput).  Items hold dtw_batch(n, w, low_latency) pairs.
+// per pair (many pairs, highest throughput).  Items hold dtw_batch(n, w, low_latency) pairs;
+// prefix (launch_items_prefix over pl.cnt) is read only when pl.cnt is set.
 // S1 (optional, [Q][ldS]): LB_Keogh^p of every pair against the query envelope qd.U/qd.L; the
 // lane-per-pair kernels then abandon on the row minimum plus the LB_Keogh terms still to come.
 // Lane-per-pair DTW of bands wider than kLaneMaxW keeps a per-wave ring of strip boundaries
