@@ -243,7 +243,7 @@ void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
     b.res = (d.k > 1 || !any) ? c.take<u64>((size_t)d.Q * d.ldres) : nullptr;
     b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.N);
     b.list2 = (d.improved && any) ? c.take<int>((size_t)d.Q * d.N) : nullptr;
-    b.counters = c.take<int>((size_t)d.Q * 4 + 8);  // cnt1, cnt2, rescnt, abandoned, spare
+    b.counters = c.take<int>((size_t)d.Q * 4);  // cnt1, cnt2, rescnt, abandoned ([4][Q])
     b.prefix = c.take<long long>((size_t)d.Q + 1);
     b.wmin = (d.from_minima && any) ? c.take<u64>((size_t)d.Q * d.nw) : nullptr;
     b.ring = (d.ring_bytes && any) ? c.take<float>(d.ring_bytes / sizeof(float)) : nullptr;
@@ -280,8 +280,8 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     const int64_t Q = d.Q, N = d.N;
     const int n = d.n, wb = d.wb, p = d.p, k = d.k;
     int *cnt1 = b.counters, *cnt2 = b.counters + Q, *rescnt = b.counters + 2 * Q, *abandoned = b.counters + 3 * Q;
-    HIPTRY(launch_fill_i32(b.counters, 0, Q * 4 + 8, s));
     if (N == 0) {  // nothing to search: every slot is empty
+        HIPTRY(launch_fill_i32(b.counters, 0, Q * 4, s));
         for (int i = 0; i <= 7; ++i) stage(i);
         HIPTRY(launch_finalize_k(b.res, 1, rescnt, Q, k, p, sp.idx, sp.dist, sp.qmap, s));
         stage(8);
@@ -293,8 +293,9 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     const lbimp_db *db = sp.db;
 
     stage(0);
-    // the envelope kernel also resets the best-so-far and threshold keys of the Q queries
-    HIPTRY(launch_envelope(sp.queries, Q, d.Qp, n, wb, b.Ue, b.Le, d.ldq, s, b.best, b.thr));
+    // the envelope kernel also resets the best-so-far and threshold keys and the four counters
+    // (cnt1, cnt2, rescnt, abandoned) of the Q queries
+    HIPTRY(launch_envelope(sp.queries, Q, d.Qp, n, wb, b.Ue, b.Le, d.ldq, s, b.best, b.thr, b.counters));
     stage(1);
     if (d.brute) {
         for (int i = 2; i <= 6; ++i) stage(i);

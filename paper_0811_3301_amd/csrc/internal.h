@@ -29,9 +29,11 @@ hipError_t launch_pack(const float *rows, int64_t N, int n, float4 *il, hipStrea
 
 // Envelope of B series (rows of length n) into rows of stride ldo; rows b in [B, Bpad) and
 // columns i in [n, ldo) are filled with U = +inf, L = -inf when ldo > n or Bpad > B.
-// keys0 / keys1, when given, receive "no key" in their first B entries.
+// keys0 / keys1, when given, receive "no key" in their first B entries; counts4 ([4][B]), when
+// given, receives 0 in all its entries.
 hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w, float *U, float *L, int ldo,
-                           hipStream_t s, unsigned long long *keys0 = nullptr, unsigned long long *keys1 = nullptr);
+                           hipStream_t s, unsigned long long *keys0 = nullptr, unsigned long long *keys1 = nullptr,
+                           int *counts4 = nullptr);
 
 // LB_Keogh^p of every interleaved candidate against Q padded envelopes (stride ld4 float4).
 // Writes out[q*ldo + c] for c < N (and +inf for c in [N, ldo) when pad_inf).  root: take the

@@ -46,13 +46,14 @@ hipError_t launch_pack(const float *rows, int64_t N, int n, float4 *il, hipStrea
 // window is cut by the series end inside one block.
 // Narrow bands (2w+1 <= kDirectWindow) take the window maximum and minimum of every output
 // directly, one output per thread, from the series in LDS: the plain definition, with no
-// serial walk.  keys0 / keys1 (optional) are set to "no key" for the B real rows, so a search
-// needs no separate fill launches for its best-so-far and threshold keys.
+// serial walk.  keys0 / keys1 (optional) are set to "no key" and counts4 (optional, [4][B])
+// to 0 for the B real rows, so a search needs no separate fill launches for its best-so-far
+// and threshold keys and its per-query counters.
 constexpr int kDirectWindow = 128;
 __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, int64_t B, int n, int w,
                                                    float *__restrict__ U, float *__restrict__ L, int ldo,
                                                    unsigned long long *__restrict__ keys0,
-                                                   unsigned long long *__restrict__ keys1) {
+                                                   unsigned long long *__restrict__ keys1, int *__restrict__ counts4) {
     extern __shared__ float sm[];
     int64_t b = blockIdx.x;
     float *Ub = U + b * (int64_t)ldo;
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, i
         if (keys0) keys0[b] = kNoKey;
         if (keys1) keys1[b] = kNoKey;
     }
+    if (counts4 && threadIdx.x < 4) counts4[threadIdx.x * B + b] = 0;
     const float *yb = y + b * (int64_t)n;
     float *gmax = sm, *gmin = sm + n, *hmax = sm + 2 * n, *hmin = sm + 3 * n;
     // The series is first copied into hmin by the whole block (coalesced), so the reads below
@@ -140,10 +142,11 @@ __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, i
 }
 
 hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w, float *U, float *L, int ldo,
-                           hipStream_t s, unsigned long long *keys0, unsigned long long *keys1) {
+                           hipStream_t s, unsigned long long *keys0, unsigned long long *keys1, int *counts4) {
     if (Bpad == 0) return hipSuccess;
     size_t lds = sizeof(float) * 4 * (size_t)n;
-    hipLaunchKernelGGL(k_envelope, dim3((unsigned)Bpad), dim3(256), lds, s, y, B, n, w, U, L, ldo, keys0, keys1);
+    hipLaunchKernelGGL(k_envelope, dim3((unsigned)Bpad), dim3(256), lds, s, y, B, n, w, U, L, ldo, keys0, keys1,
+                       counts4);
     return hipGetLastError();
 }
 
