@@ -18,6 +18,7 @@ GPU; ``GpuExecutor`` drives the HIP library through its C-ABI binding.
 """
 from __future__ import annotations
 
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -259,6 +260,29 @@ def serve(requests, executor, budget_bytes: int, max_batch: int = 512, clock=tim
     # the workspace of a batch does not depend on the slot (all contexts share one device)
     sched = Scheduler(budget, max_batch, lambda reqs: executor.need(0, reqs))
     results = []
+    n = len(requests)
+    # The cyclic garbage collector stays off while the loop runs: a full collection over the
+    # request and result objects pauses the loop for tens of milliseconds (measured p99 at
+    # 20k requests/s: 70 ms with it, 10 ms without).  Requests and results hold no reference
+    # cycles, so reference counting frees them; the collector's state is restored afterwards.
+    gc_was_enabled = gc.isenabled()
+    gc.disable()
+    try:
+        t_end = _serve_loop(requests, executor, budget, sched, results, clock, idle_sleep)
+    finally:
+        if gc_was_enabled:
+            gc.enable()
+    first = requests[0].t_arrive if n else 0.0
+    summary = latency_summary(results)
+    summary.update(requests=n, seconds=t_end - first, qps=n / max(t_end - first, 1e-9),
+                   offered_qps=(n / max(requests[-1].t_arrive - first, 1e-9)) if n > 1 else None,
+                   workspace_bytes=int(sum(budget.held)))
+    return results, summary
+
+
+def _serve_loop(requests, executor, budget, sched, results, clock, idle_sleep) -> float:
+    """The real-time loop of ``serve``: appends to ``results``; returns its length in seconds."""
+    slots = len(executor.slots)
     nxt = 0
     n = len(requests)
     t0 = clock()
@@ -287,10 +311,4 @@ def serve(requests, executor, budget_bytes: int, max_batch: int = 512, clock=tim
                 raise RuntimeError("a request needs more device memory than the budget allows")
             if idle_sleep:
                 time.sleep(idle_sleep)
-    t_end = clock() - t0
-    first = requests[0].t_arrive if n else 0.0
-    summary = latency_summary(results)
-    summary.update(requests=n, seconds=t_end - first, qps=n / max(t_end - first, 1e-9),
-                   offered_qps=(n / max(requests[-1].t_arrive - first, 1e-9)) if n > 1 else None,
-                   workspace_bytes=int(sum(budget.held)))
-    return results, summary
+    return clock() - t0

@@ -75,3 +75,60 @@ def test_serving_workload_stream():
     assert set(np.unique(req["k"])) == {1, 5, 10}
     assert set(np.unique(req["w"])) == {13, 26}                   # w = 0.1 n
     assert all(len(y) == (128, 256)[b] for y, b in zip(req["y"], req["db"]))
+
+
+class _InstantExecutor:
+    """Stand-in for the GPU executor: a launched batch is done at the next poll.  Records
+    whether the cyclic garbage collector was on at each launch."""
+
+    def __init__(self, slots=2, fail_at=None):
+        self.slots = [None] * slots
+        self.busy = {}
+        self.gc_at_launch = []
+        self.fail_at = fail_at
+
+    def held(self, slot):
+        return 0
+
+    def need(self, slot, reqs):
+        return len(reqs)
+
+    def free_slots(self):
+        return [i for i in range(len(self.slots)) if i not in self.busy]
+
+    def launch(self, slot, reqs, now):
+        import gc
+        self.gc_at_launch.append(gc.isenabled())
+        if self.fail_at is not None and len(self.gc_at_launch) > self.fail_at:
+            raise RuntimeError("launch failed")
+        self.busy[slot] = (list(reqs), now)
+
+    def poll(self, now_fn):
+        out = []
+        for slot, (reqs, t_admit) in list(self.busy.items()):
+            t = now_fn()
+            out += [Result(r.rid, np.zeros(r.k, np.int64), np.zeros(r.k, np.float32), r.t_arrive, t_admit, t)
+                    for r in reqs]
+            del self.busy[slot]
+        return out
+
+
+@pytest.mark.parametrize("enabled_before", [True, False])
+def test_serve_runs_with_cyclic_gc_off_and_restores_it(enabled_before):
+    import gc
+    from paper_0811_3301_amd.serve import serve
+    ex = _InstantExecutor()
+    reqs = _reqs(40)
+    was = gc.isenabled()
+    try:
+        (gc.enable if enabled_before else gc.disable)()
+        results, summary = serve(reqs, ex, budget_bytes=10**6, max_batch=8, idle_sleep=0)
+        assert sorted(r.rid for r in results) == list(range(40)) and summary["requests"] == 40
+        assert ex.gc_at_launch and not any(ex.gc_at_launch)
+        assert gc.isenabled() == enabled_before
+        # an error inside the loop restores the collector too
+        with pytest.raises(RuntimeError):
+            serve(_reqs(40), _InstantExecutor(fail_at=1), budget_bytes=10**6, max_batch=8, idle_sleep=0)
+        assert gc.isenabled() == enabled_before
+    finally:
+        (gc.enable if was else gc.disable)()
