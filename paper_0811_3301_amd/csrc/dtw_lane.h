@@ -35,9 +35,9 @@ __device__ __forceinline__ void dtw_row(float (&D)[2 * W + 1], float xi, const f
 // R rows at once in skewed order: step s updates cell k = s - r of row r, rows ascending.
 // The in-place reads are unchanged -- when (r, k) runs, D[k] and D[k+1] still hold row r-1
 // and D[k-1] already holds row r -- but the R dependency chains interleave, which hides the
-// latency of the serial left-to-right chain of each row.  More rows hide more latency, but a
-// band wider than w = 32 at eight rows unrolls past the point where the compiler keeps D in
-// registers (it moves the array to scratch memory), so wide bands take four rows per step.
+// latency of the serial left-to-right chain of each row.  More rows hide more latency, but
+// past about 520 unrolled cells per step the compiler stops keeping D in registers (it moves
+// the array to scratch memory): eight rows up to w = 32, six up to w = 53, four above.
 template <int P, int W, int R>
 __device__ __forceinline__ void dtw_rowsR(float (&D)[2 * W + 1], const float (&xs)[R], const float *yrow0) {
     constexpr int BW = 2 * W + 1;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void dtw_rowsR(float (&D)[2 * W + 1], const float (&x
     }
 }
 
-constexpr int lane_rows(int w) { return w <= 32 ? 8 : 4; }
+constexpr int lane_rows(int w) { return w <= 32 ? 8 : w <= 53 ? 6 : 4; }
 
 template <int P, int W, bool CASCADE>
 __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
