@@ -152,21 +152,25 @@ int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, in
 int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                     int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
 
-/* A ragged batch: Q queries of mixed lengths, bands and databases in one call (the search
+/* A ragged batch: Q queries of mixed lengths, bands, databases and k in one call (the search
  * of Algorithms 2 and 3 for each query; batching changes no result).
  *   dbs       host [ndb] database handles (lengths may differ);
  *   queries   device, the queries packed end to end; query q occupies
  *             queries[offsets[q] .. offsets[q+1]) and its length must equal the length of
  *             database dbs[db_of[q]];
  *   offsets   host [Q+1] int64 element offsets; db_of host [Q]; w host [Q] bands;
- *   idx, dist device [Q][k], row q for query q, as in lbimp_nn_search; stats host [Q] or NULL.
- * Queries sharing a database and an effective band min(w, n-1) form one group; the groups
- * run concurrently on the context's streams, ordered after earlier work on its stream and
- * before later work.  The host arrays may be reused once the call returns.  Calls of
- * one context must not overlap (they share its workspace); one context per host thread. */
+ *   k         host [Q] neighbours per query, each in [1, 64];
+ *   idx, dist device [Q][kmax] with kmax = max_q k[q]: row q holds query q's k[q] nearest
+ *             neighbours sorted as in lbimp_nn_search, then idx -1 / dist +inf up to kmax;
+ *   stats     host [Q] or NULL.
+ * Queries sharing a database and an effective band min(w, n-1) form one group, searched once
+ * for the group's largest k with each query's threshold set by its own k; the groups run
+ * concurrently on the context's streams, ordered after earlier work on its stream and before
+ * later work.  The host arrays may be reused once the call returns.  Calls of one context
+ * must not overlap (they share its workspace); one context per host thread. */
 int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, const float *queries,
                            const int64_t *offsets, const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p,
-                           int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
+                           const int32_t *k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
 
 /* Autotuner.  Runs the search of this batch (arguments as lbimp_nn_search) under candidate
  * choices that change speed and never results -- the number of seeding DTWs, the LB_Keogh
@@ -194,8 +198,8 @@ int lbimp_ctx_copy_tuning(lbimp_ctx *dst, const lbimp_ctx *src);
  * size.  A serving loop uses it to admit batches against a device-memory budget before
  * launching them. */
 int lbimp_nn_search_ragged_workspace(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb,
-                                     const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p, int32_t k,
-                                     int32_t mode, uint64_t *bytes);
+                                     const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p,
+                                     const int32_t *k, int32_t mode, uint64_t *bytes);
 
 /* Device workspace currently held by the context (it grows on demand and is freed with the
  * context), written to *bytes. */

@@ -190,6 +190,8 @@ struct SearchSpec {  // Q queries of one length against one database
     float *dist;
     const int64_t *qmap;   // device [Q] output rows, or nullptr for the identity
     Knobs kn;
+    const int64_t *kq = nullptr;  // device [Q] per-query k (each <= k), or nullptr: k for every query
+    int ldo = 0;                  // output row stride in entries (0: k)
 };
 
 struct SearchDims {
@@ -279,11 +281,12 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     };
     const int64_t Q = d.Q, N = d.N;
     const int n = d.n, wb = d.wb, p = d.p, k = d.k;
+    const int ldo = sp.ldo ? sp.ldo : k;
     int *cnt1 = b.counters, *cnt2 = b.counters + Q, *rescnt = b.counters + 2 * Q, *abandoned = b.counters + 3 * Q;
     if (N == 0) {  // nothing to search: every slot is empty
         HIPTRY(launch_fill_i32(b.counters, 0, Q * 4, s));
         for (int i = 0; i <= 7; ++i) stage(i);
-        HIPTRY(launch_finalize_k(b.res, 1, rescnt, Q, k, p, sp.idx, sp.dist, sp.qmap, s));
+        HIPTRY(launch_finalize_k(b.res, 1, rescnt, Q, k, sp.kq, ldo, p, sp.idx, sp.dist, sp.qmap, s));
         stage(8);
         return LBIMP_OK;
     }
@@ -317,7 +320,7 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         HIPTRY(launch_dtw(p, db->rows, n, wb, qd, seedl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
                           k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, seed_ll, b.ring,
                           d.ring_bytes, nullptr, 0, s));
-        if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, b.thr, s));
+        if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, sp.kq, b.thr, s));
         stage(4);
         HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
         stage(5);
@@ -337,9 +340,9 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     }
     stage(7);
     if (k == 1)
-        HIPTRY(launch_finalize1(b.best, Q, p, sp.idx, sp.dist, sp.qmap, s));
+        HIPTRY(launch_finalize1(b.best, Q, p, sp.idx, sp.dist, sp.qmap, ldo, s));
     else
-        HIPTRY(launch_finalize_k(b.res, d.ldres, rescnt, Q, k, p, sp.idx, sp.dist, sp.qmap, s));
+        HIPTRY(launch_finalize_k(b.res, d.ldres, rescnt, Q, k, sp.kq, ldo, p, sp.idx, sp.dist, sp.qmap, s));
     stage(8);
     return LBIMP_OK;
 }
@@ -570,18 +573,22 @@ struct RaggedPlan {
     std::vector<SearchDims> dims;
     std::vector<SearchBufs> bufs;
     std::vector<float *> qbuf;
-    std::vector<int64_t *> qmap, qsrc;
+    std::vector<int64_t *> qmap, qsrc, kq;
+    std::vector<bool> mixed_k;  // the group's queries ask for different k
+    int kmax = 1;               // output row stride: the largest k of the batch
     size_t meta_elems = 0;
     int64_t *meta = nullptr;
 
-    // workspace: [metadata: per group query ids, then source offsets][per group: queries + search]
+    // workspace: [metadata: per group query ids, source offsets, k of each query]
+    //            [per group: queries + search]
     void carve(Carver &c) {
         meta = c.take<int64_t>(meta_elems);
         size_t o = 0;
         for (size_t g = 0; g < specs.size(); ++g) {
             qmap[g] = meta ? meta + o : nullptr;
             qsrc[g] = meta ? meta + o + specs[g].Q : nullptr;
-            o += 2 * (size_t)specs[g].Q;
+            kq[g] = meta ? meta + o + 2 * specs[g].Q : nullptr;
+            o += 3 * (size_t)specs[g].Q;
         }
         for (size_t g = 0; g < specs.size(); ++g) {
             qbuf[g] = c.take<float>((size_t)specs[g].Q * dims[g].n);
@@ -591,9 +598,9 @@ struct RaggedPlan {
 };
 
 static int plan_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, const int64_t *offsets,
-                       const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p, int32_t k, int32_t mode,
+                       const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p, const int32_t *k, int32_t mode,
                        int64_t *idx, float *dist, RaggedPlan &plan) {
-    if (!dbs || ndb < 1 || !db_of || !w) return fail(LBIMP_E_INVALID, "null pointer or no database");
+    if (!dbs || ndb < 1 || !db_of || !w || !k) return fail(LBIMP_E_INVALID, "null pointer or no database");
     for (int i = 0; i < ndb; ++i) {
         if (!dbs[i]) return fail(LBIMP_E_INVALID, "null database %d", i);
         if (dbs[i]->device != ctx->device) return fail(LBIMP_E_INVALID, "database %d lives on another device", i);
@@ -607,8 +614,9 @@ static int plan_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, 
                 return fail(LBIMP_E_INVALID, "query %lld: length %lld, database length %d", (long long)q,
                             (long long)len, dbs[b]->n);
         }
-        if (int r = check_search(1, dbs[b]->n, w[q], p, k, mode)) return r;
+        if (int r = check_search(1, dbs[b]->n, w[q], p, k[q], mode)) return r;
         plan.groups[{b, band_of(dbs[b]->n, w[q])}].push_back(q);
+        plan.kmax = std::max(plan.kmax, (int)k[q]);
     }
     const size_t G = plan.groups.size();
     plan.dims.resize(G);
@@ -616,14 +624,25 @@ static int plan_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, 
     plan.qbuf.resize(G);
     plan.qmap.resize(G);
     plan.qsrc.resize(G);
+    plan.kq.resize(G);
+    plan.mixed_k.resize(G);
     plan.specs.reserve(G);
     for (auto &kv : plan.groups) {
         const int64_t Qg = (int64_t)kv.second.size();
         const lbimp_db *db = dbs[kv.first.first];
-        plan.specs.push_back(SearchSpec{db, nullptr, Qg, kv.first.second, p, k, mode, idx, dist, nullptr,
-                                        knobs_for(ctx, db, Qg, kv.first.second, p, k, mode)});
+        int kg = 1;  // the group runs as one search for its largest k; each query keeps its own k
+        bool mixed = false;
+        for (int64_t q : kv.second) {
+            mixed |= k[q] != k[kv.second[0]];
+            kg = std::max(kg, (int)k[q]);
+        }
+        plan.mixed_k[plan.specs.size()] = mixed;
+        SearchSpec sp{db, nullptr, Qg, kv.first.second, p, kg, mode, idx, dist, nullptr,
+                      knobs_for(ctx, db, Qg, kv.first.second, p, kg, mode)};
+        sp.ldo = plan.kmax;
+        plan.specs.push_back(sp);
         if (int r = dims_of(plan.specs.back(), ctx->num_cu, plan.dims[plan.specs.size() - 1])) return r;
-        plan.meta_elems += 2 * (size_t)Qg;
+        plan.meta_elems += 3 * (size_t)Qg;
     }
     return LBIMP_OK;
 }
@@ -936,7 +955,7 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
 
 int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, const float *queries,
                            const int64_t *offsets, const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p,
-                           int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats) {
+                           const int32_t *k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats) {
     if (int r = check_ctx(ctx)) return r;
     if (Q < 0) return fail(LBIMP_E_INVALID, "negative query count");
     if (Q == 0) return LBIMP_OK;
@@ -947,12 +966,13 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         bool tuned_any = false;
         for (size_t g = 0; g < plan.specs.size(); ++g) {
             const SearchSpec &sp = plan.specs[g];
-            if (sp.db->N == 0 || ctx->tuned.count(tune_key(sp.db, sp.Q, sp.w, p, k, mode))) continue;
+            if (sp.db->N == 0 || ctx->tuned.count(tune_key(sp.db, sp.Q, sp.w, p, sp.k, mode))) continue;
             const std::vector<int64_t> &ids = std::next(plan.groups.begin(), g)->second;
             std::vector<int64_t> off(ids.size());
             for (size_t i = 0; i < ids.size(); ++i) off[i] = offsets[ids[i]];
             Knobs kn;
-            if (int r = tune_search(ctx, sp.db, nullptr, queries, off.data(), sp.Q, sp.w, p, k, mode, &kn)) return r;
+            if (int r = tune_search(ctx, sp.db, nullptr, queries, off.data(), sp.Q, sp.w, p, sp.k, mode, &kn))
+                return r;
             tuned_any = true;
         }
         if (tuned_any) {
@@ -986,6 +1006,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         for (auto &kv : groups) {
             for (int64_t q : kv.second) h[o++] = q;
             for (int64_t q : kv.second) h[o++] = offsets[q];
+            for (int64_t q : kv.second) h[o++] = k[q];
         }
         HIPTRY(hipMemcpyAsync(meta, h, meta_elems * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
         HIPTRY(hipEventRecord(pc->ev, ctx->stream));
@@ -998,6 +1019,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     for (int g = 0; g < G; ++g) {
         specs[g].queries = qbuf[g];
         specs[g].qmap = qmap[g];
+        specs[g].kq = plan.mixed_k[g] ? plan.kq[g] : nullptr;
     }
     // the groups run concurrently on the context's stream pool, captured once as a graph and
     // replayed while the call's signature (pointers, shapes, grouping, workspace) is unchanged
@@ -1026,7 +1048,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     mix((uint64_t)(uintptr_t)idx);
     mix((uint64_t)(uintptr_t)dist);
     mix((uint64_t)Q);
-    mix((uint64_t)(p * 131 + k * 7 + mode));
+    mix((uint64_t)(p * 131 + plan.kmax * 7 + mode));
     mix((uint64_t)width);
     for (int g = 0; g < G; ++g) {
         const lbimp_db *db = specs[g].db;  // a database freed and recreated may reuse an address
@@ -1037,6 +1059,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         mix((uint64_t)db->n);
         mix((uint64_t)specs[g].Q);
         mix((uint64_t)specs[g].w);
+        mix((uint64_t)(specs[g].k * 2 + (plan.mixed_k[g] ? 1 : 0)));
         const Knobs &kn = specs[g].kn;
         mix((uint64_t)(kn.seeds * 1000000 + kn.sweep_shape * 10000 + kn.lbi_pipeline * 1000 + kn.dtw_group * 100 +
                        kn.seed_lane * 10 + kn.cascade));
@@ -1111,8 +1134,8 @@ int lbimp_ctx_copy_tuning(lbimp_ctx *dst, const lbimp_ctx *src) {
 }
 
 int lbimp_nn_search_ragged_workspace(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb,
-                                     const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p, int32_t k,
-                                     int32_t mode, uint64_t *bytes) {
+                                     const int32_t *db_of, const int32_t *w, int64_t Q, int32_t p,
+                                     const int32_t *k, int32_t mode, uint64_t *bytes) {
     if (int r = check_ctx(ctx)) return r;
     if (!bytes) return fail(LBIMP_E_INVALID, "null output pointer");
     *bytes = 0;

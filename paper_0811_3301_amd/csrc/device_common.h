@@ -1,8 +1,6 @@
 // Device helpers shared by the persistent second-pass and DTW kernels.
 #pragma once
 
-#include <vector>
-
 #include "internal.h"
 
 namespace lbimp {
@@ -122,23 +120,28 @@ __device__ __forceinline__ void stage_lds(float *dst, int count, F value_at) {
 // Grid of a persistent kernel: as many one-wave blocks as fit on the chip at once.
 template <class Kernel>
 inline int persistent_grid(Kernel k, size_t lds, int num_cu) {
-    // occupancy queries cost microseconds each; remember them per (kernel, LDS size, device)
+    // occupancy queries cost microseconds each; remember them per (kernel, LDS size, device) in a
+    // fixed table, so that launching never allocates host memory
     struct Entry {
         const void *k;
         size_t lds;
         int device, per_cu;
     };
-    static thread_local std::vector<Entry> cache;
+    constexpr int kCache = 512;
+    static thread_local Entry cache[kCache];
+    static thread_local int cached = 0;
     int device = 0;
     (void)hipGetDevice(&device);
-    for (const Entry &e : cache)
+    for (int i = 0; i < cached; ++i) {
+        const Entry &e = cache[i];
         if (e.k == reinterpret_cast<const void *>(k) && e.lds == lds && e.device == device) return num_cu * e.per_cu;
+    }
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64, lds) != hipSuccess || per_cu < 1) {
         (void)hipGetLastError();
         per_cu = 4;
     }
-    if (cache.size() < 4096) cache.push_back(Entry{reinterpret_cast<const void *>(k), lds, device, per_cu});
+    if (cached < kCache) cache[cached++] = Entry{reinterpret_cast<const void *>(k), lds, device, per_cu};
     return num_cu * per_cu;
 }
 

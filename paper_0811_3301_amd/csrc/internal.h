@@ -111,16 +111,19 @@ hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, Pair
                       bool abandon, bool low_latency, float *ring, size_t ring_bytes, const float *S1,
                       int64_t ldS, hipStream_t s);
 
-// k-th smallest key of res[q][0..min(rescnt[q], 64)) into thr[q] (kNoKey if fewer than k).
+// k-th smallest key of res[q][0..min(rescnt[q], 64)) into thr[q] (kNoKey if fewer than k), with
+// k = kq[q] when kq (device [Q]) is given.
 hipError_t launch_kth_key(const unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k,
-                          unsigned long long *thr, hipStream_t s);
+                          const int64_t *kq, unsigned long long *thr, hipStream_t s);
 
-// 1-NN outputs from best keys, or k-NN outputs by selecting the k smallest of res[q].  Query q
-// writes output row qmap[q] (or q when qmap is null).
+// 1-NN outputs from best keys, or k-NN outputs by selecting the k smallest of res[q] (k = kq[q]
+// when kq is given).  Query q writes output row qmap[q] (or q when qmap is null) of ldo entries;
+// entries past its k get idx -1 and dist +inf.
 hipError_t launch_finalize1(const unsigned long long *best, int64_t Q, int p, int64_t *idx, float *dist,
-                            const int64_t *qmap, hipStream_t s);
-hipError_t launch_finalize_k(unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k, int p,
-                             int64_t *idx, float *dist, const int64_t *qmap, hipStream_t s);
+                            const int64_t *qmap, int ldo, hipStream_t s);
+hipError_t launch_finalize_k(unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k,
+                             const int64_t *kq, int ldo, int p, int64_t *idx, float *dist, const int64_t *qmap,
+                             hipStream_t s);
 
 // dst[j][i] = src[off[j] + i] for j < count, i < n (gathers equal-length rows of a packed array).
 hipError_t launch_gather_rows(const float *src, const int64_t *off, int n, int64_t count, float *dst, hipStream_t s);

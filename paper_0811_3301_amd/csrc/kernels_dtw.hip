@@ -249,12 +249,15 @@ hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, Pair
 }
 
 // ------------------------------------------------------------------ thresholds and results
-// 64-entry bitonic sort in LDS of one query's first min(cnt, 64) keys.
+// 64-entry bitonic sort in LDS of one query's first min(cnt, 64) keys; the threshold is the
+// k-th smallest, with k = kq[q] when a per-query array is given.
 __global__ __launch_bounds__(64) void k_kth_key(const u64 *__restrict__ res, int64_t ldres,
-                                                const int *__restrict__ rescnt, int k, u64 *__restrict__ thr) {
+                                                const int *__restrict__ rescnt, int k, const int64_t *__restrict__ kq,
+                                                u64 *__restrict__ thr) {
     __shared__ u64 keys[64];
     const int64_t q = blockIdx.x;
     const int cnt = min(rescnt[q], 64);
+    const int kk = kq ? (int)kq[q] : k;
     keys[threadIdx.x] = threadIdx.x < cnt ? res[q * ldres + threadIdx.x] : kNoKey;
     __syncthreads();
     for (int size = 2; size <= 64; size <<= 1) {
@@ -273,13 +276,13 @@ __global__ __launch_bounds__(64) void k_kth_key(const u64 *__restrict__ res, int
             __syncthreads();
         }
     }
-    if (threadIdx.x == 0) thr[q] = (cnt >= k) ? keys[k - 1] : kNoKey;
+    if (threadIdx.x == 0) thr[q] = (cnt >= kk) ? keys[kk - 1] : kNoKey;
 }
 
 hipError_t launch_kth_key(const unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k,
-                          unsigned long long *thr, hipStream_t s) {
+                          const int64_t *kq, unsigned long long *thr, hipStream_t s) {
     if (Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kth_key, dim3((unsigned)Q), dim3(64), 0, s, res, ldres, rescnt, k, thr);
+    hipLaunchKernelGGL(k_kth_key, dim3((unsigned)Q), dim3(64), 0, s, res, ldres, rescnt, k, kq, thr);
     return hipGetLastError();
 }
 
@@ -288,12 +291,13 @@ __device__ __forceinline__ float key_root(u64 key, int p) {
     return p == 1 ? v : sqrtf(v);
 }
 
+// Output row r holds ldo entries: the best key in entry 0, -1 / +inf in the others.
 __global__ void k_finalize1(const u64 *__restrict__ best, int64_t Q, int p, int64_t *__restrict__ idx,
-                            float *__restrict__ dist, const int64_t *__restrict__ qmap) {
+                            float *__restrict__ dist, const int64_t *__restrict__ qmap, int ldo) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= Q) return;
     const u64 key = best[q];
-    const int64_t row = qmap ? qmap[q] : q;
+    const int64_t row = (qmap ? qmap[q] : q) * ldo;
     if (key == kNoKey) {
         idx[row] = -1;
         dist[row] = kInf;
@@ -301,12 +305,17 @@ __global__ void k_finalize1(const u64 *__restrict__ best, int64_t Q, int p, int6
         idx[row] = (int64_t)(key & 0xffffffffu);
         dist[row] = key_root(key, p);
     }
+    for (int r = 1; r < ldo; ++r) {
+        idx[row + r] = -1;
+        dist[row + r] = kInf;
+    }
 }
 
 hipError_t launch_finalize1(const unsigned long long *best, int64_t Q, int p, int64_t *idx, float *dist,
-                            const int64_t *qmap, hipStream_t s) {
+                            const int64_t *qmap, int ldo, hipStream_t s) {
     if (Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize1, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s, best, Q, p, idx, dist, qmap);
+    hipLaunchKernelGGL(k_finalize1, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s, best, Q, p, idx, dist, qmap,
+                       ldo);
     return hipGetLastError();
 }
 
@@ -326,16 +335,21 @@ hipError_t launch_gather_rows(const float *src, const int64_t *off, int n, int64
     return hipGetLastError();
 }
 
-// k rounds of a block-wide minimum; each selected key is removed before the next round.
+// k rounds of a block-wide minimum (k = kq[q] when a per-query array is given); each
+// selected key is removed before the next round.  Entries k .. ldo-1 of the output row get
+// -1 / +inf.
 __global__ __launch_bounds__(256) void k_finalize_k(u64 *__restrict__ res, int64_t ldres,
-                                                    const int *__restrict__ rescnt, int k, int p,
+                                                    const int *__restrict__ rescnt, int k,
+                                                    const int64_t *__restrict__ kq, int ldo, int p,
                                                     int64_t *__restrict__ idx, float *__restrict__ dist,
                                                     const int64_t *__restrict__ qmap) {
     __shared__ u64 red[256];
     const int64_t q = blockIdx.x;
     const int cnt = rescnt[q];
+    const int kk = kq ? (int)kq[q] : k;
+    const int64_t row = (qmap ? qmap[q] : q) * ldo;
     u64 *r = res + q * ldres;
-    for (int round = 0; round < k; ++round) {
+    for (int round = 0; round < kk; ++round) {
         u64 m = kNoKey;
         for (int t = threadIdx.x; t < cnt; t += 256) m = min(m, r[t]);
         red[threadIdx.x] = m;
@@ -351,18 +365,23 @@ __global__ __launch_bounds__(256) void k_finalize_k(u64 *__restrict__ res, int64
                 if (r[t] == best) r[t] = kNoKey;
         }
         if (threadIdx.x == 0) {
-            const int64_t row = qmap ? qmap[q] : q;
-            idx[row * k + round] = best == kNoKey ? -1 : (int64_t)(best & 0xffffffffu);
-            dist[row * k + round] = best == kNoKey ? kInf : key_root(best, p);
+            idx[row + round] = best == kNoKey ? -1 : (int64_t)(best & 0xffffffffu);
+            dist[row + round] = best == kNoKey ? kInf : key_root(best, p);
         }
         __syncthreads();
     }
+    for (int t = kk + threadIdx.x; t < ldo; t += 256) {
+        idx[row + t] = -1;
+        dist[row + t] = kInf;
+    }
 }
 
-hipError_t launch_finalize_k(unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k, int p,
-                             int64_t *idx, float *dist, const int64_t *qmap, hipStream_t s) {
+hipError_t launch_finalize_k(unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k,
+                             const int64_t *kq, int ldo, int p, int64_t *idx, float *dist, const int64_t *qmap,
+                             hipStream_t s) {
     if (Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize_k, dim3((unsigned)Q), dim3(256), 0, s, res, ldres, rescnt, k, p, idx, dist, qmap);
+    hipLaunchKernelGGL(k_finalize_k, dim3((unsigned)Q), dim3(256), 0, s, res, ldres, rescnt, k, kq, ldo, p, idx,
+                       dist, qmap);
     return hipGetLastError();
 }
 

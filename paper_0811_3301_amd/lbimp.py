@@ -54,10 +54,10 @@ SIGNATURES = {
     "lbimp_nn_search": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp,
                                        ctypes.POINTER(LbimpStats)]),
     "lbimp_nn_search_ragged": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i32, _vp, ctypes.POINTER(_i64),
-                                              ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i64, _i32, _i32, _i32,
-                                              _vp, _vp, ctypes.POINTER(LbimpStats)]),
+                                              ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i64, _i32,
+                                              ctypes.POINTER(_i32), _i32, _vp, _vp, ctypes.POINTER(LbimpStats)]),
     "lbimp_nn_search_ragged_workspace": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i32),
-                                                        ctypes.POINTER(_i32), _i64, _i32, _i32, _i32,
+                                                        ctypes.POINTER(_i32), _i64, _i32, ctypes.POINTER(_i32), _i32,
                                                         ctypes.POINTER(ctypes.c_uint64)]),
     "lbimp_ctx_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
     "lbimp_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32)]),
@@ -254,11 +254,19 @@ def _stats_array(st, Q):
         Q, len(STATS_FIELDS))
 
 
-def lbimp_nn_search_ragged(ctx: Ctx, dbs, queries: torch.Tensor, offsets, db_of, w, p: int, k: int = 1,
+def _per_query(v, Q, name):
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.int32), (Q,)))
+    if a.shape != (Q,):
+        raise ValueError(f"{name} must be one value or one per query")
+    return a
+
+
+def lbimp_nn_search_ragged(ctx: Ctx, dbs, queries: torch.Tensor, offsets, db_of, w, p: int, k=1,
                            mode="improved", idx=None, dist=None, stats: bool = True):
     """Ragged batch: `queries` is a 1-D device tensor holding the queries end to end, query q at
-    [offsets[q], offsets[q+1]); db_of[q] indexes `dbs`; w is one band or one per query.
-    Returns (idx [Q][k], dist [Q][k], stats) as lbimp_nn_search does."""
+    [offsets[q], offsets[q+1]); db_of[q] indexes `dbs`; w and k are one value or one per query.
+    Returns (idx [Q][kmax], dist [Q][kmax], stats) with kmax the largest k; row q holds query
+    q's k nearest neighbours, then -1 / +inf."""
     if isinstance(mode, str):
         mode = MODES[mode]
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -266,33 +274,37 @@ def lbimp_nn_search_ragged(ctx: Ctx, dbs, queries: torch.Tensor, offsets, db_of,
     if Q < 0:
         raise ValueError("offsets must hold Q + 1 entries")
     dof = np.ascontiguousarray(db_of, dtype=np.int32)
-    wq = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.int32), (Q,)))
+    wq = _per_query(w, Q, "w")
+    kq = _per_query(k, Q, "k")
     if dof.shape != (Q,):
         raise ValueError("db_of must hold Q entries")
-    idx = _out(idx, (Q, k), torch.int64, queries)
-    dist = _out(dist, (Q, k), torch.float32, queries)
+    kmax = int(kq.max()) if Q else 1
+    idx = _out(idx, (Q, kmax), torch.int64, queries)
+    dist = _out(dist, (Q, kmax), torch.float32, queries)
     handles = (_vp * max(len(dbs), 1))(*[d.h for d in dbs])
     st = (LbimpStats * max(Q, 1))() if stats else None
     _check(_lib.lbimp_nn_search_ragged(
         ctx.sync_stream(), handles, len(dbs), _dev(queries, "queries") if queries.numel() else None,
         off.ctypes.data_as(ctypes.POINTER(_i64)), dof.ctypes.data_as(ctypes.POINTER(_i32)),
-        wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p, k, mode, _dev(idx, "idx", torch.int64), _dev(dist, "dist"),
-        st), "lbimp_nn_search_ragged")
+        wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p, kq.ctypes.data_as(ctypes.POINTER(_i32)), mode,
+        _dev(idx, "idx", torch.int64), _dev(dist, "dist"), st), "lbimp_nn_search_ragged")
     return idx, dist, (_stats_array(st, Q) if stats else None)
 
 
-def lbimp_nn_search_ragged_workspace(ctx: Ctx, dbs, db_of, w, p: int, k: int = 1, mode="improved") -> int:
+def lbimp_nn_search_ragged_workspace(ctx: Ctx, dbs, db_of, w, p: int, k=1, mode="improved") -> int:
     """Device workspace (bytes) lbimp_nn_search_ragged needs for this batch on `ctx`."""
     if isinstance(mode, str):
         mode = MODES[mode]
     dof = np.ascontiguousarray(db_of, dtype=np.int32)
     Q = dof.shape[0]
-    wq = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.int32), (Q,)))
+    wq = _per_query(w, Q, "w")
+    kq = _per_query(k, Q, "k")
     handles = (_vp * max(len(dbs), 1))(*[d.h for d in dbs])
     out = ctypes.c_uint64(0)
     _check(_lib.lbimp_nn_search_ragged_workspace(ctx.h, handles, len(dbs), dof.ctypes.data_as(ctypes.POINTER(_i32)),
-                                                 wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p, k, mode,
-                                                 ctypes.byref(out)), "lbimp_nn_search_ragged_workspace")
+                                                 wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p,
+                                                 kq.ctypes.data_as(ctypes.POINTER(_i32)), mode, ctypes.byref(out)),
+           "lbimp_nn_search_ragged_workspace")
     return int(out.value)
 
 

@@ -10,8 +10,8 @@ cut down, and a request that fits nowhere waits for a slot with enough memory.
 
 Each request's answer is the one ``lbimp_nn_search`` gives for it alone: batching only
 changes which kernels run side by side (the distance of every pair is computed by the same
-arithmetic, and the k nearest keys are a property of the set).  A batch holding several k
-values is searched once per distinct k.
+arithmetic, and the k nearest keys are a property of the set).  A batch is one ragged search
+whatever the mix of lengths, bands and k of its requests.
 
 The scheduling policy (``Scheduler``, ``MemoryBudget``) is plain Python and runs without a
 GPU; ``GpuExecutor`` drives the HIP library through its C-ABI binding.
@@ -121,7 +121,7 @@ class _Slot:
     dist_h: object
     event: object = None
     batch: list = field(default_factory=list)
-    classes: list = field(default_factory=list)
+    kb: int = 1                 # output row stride of the batch in flight (its largest k)
     t_admit: float = 0.0
     busy: bool = False
 
@@ -175,14 +175,9 @@ class GpuExecutor:
         torch.cuda.synchronize()
 
     def need(self, slot: int, reqs) -> int:
-        """Largest workspace among the batch's per-k searches on this slot."""
-        ctx = self.slots[slot].ctx
-        best = 0
-        for k in sorted({r.k for r in reqs}):
-            sub = [r for r in reqs if r.k == k]
-            best = max(best, self.L.lbimp_nn_search_ragged_workspace(
-                ctx, self.dbs, [r.db for r in sub], [r.w for r in sub], self.p, k, self.mode))
-        return best
+        """Workspace of the batch's ragged search on this slot."""
+        return self.L.lbimp_nn_search_ragged_workspace(self.slots[slot].ctx, self.dbs, [r.db for r in reqs],
+                                                       [r.w for r in reqs], self.p, [r.k for r in reqs], self.mode)
 
     def held(self, slot: int) -> int:
         return self.L.lbimp_ctx_workspace_bytes(self.slots[slot].ctx)
@@ -195,33 +190,25 @@ class GpuExecutor:
         s = self.slots[slot]
         if len(reqs) > self.max_batch or any(r.k > self.kmax for r in reqs):
             raise ValueError("batch exceeds the executor's preallocated sizes")
-        # queries of one k are contiguous, so each search reads its queries in place by offsets
-        reqs = sorted(reqs, key=lambda r: r.k)
         offsets = np.zeros(len(reqs) + 1, dtype=np.int64)
         np.cumsum([len(r.y) for r in reqs], out=offsets[1:])
         host = s.qhost.numpy()
         for r, o in zip(reqs, offsets[:-1]):
             host[o:o + len(r.y)] = r.y
         total = int(offsets[-1])
-        ks = np.array([r.k for r in reqs])
-        classes = []  # (k, first row, end row): rows of the batch, outputs at flat offset first*kmax
-        for k in np.unique(ks):
-            rows = np.nonzero(ks == k)[0]
-            classes.append((int(k), int(rows[0]), int(rows[-1]) + 1))
+        ks = [r.k for r in reqs]
+        kb = max(ks)  # output rows of the batch: each request's k nearest, then -1 / +inf up to kb
+        used = len(reqs) * kb
         with torch.cuda.stream(s.stream):
             s.qbuf[:total].copy_(s.qhost[:total], non_blocking=True)
-            for k, lo, hi in classes:
-                base = lo * self.kmax
-                out_i = s.idx.view(-1)[base:base + (hi - lo) * k].view(hi - lo, k)
-                out_d = s.dist.view(-1)[base:base + (hi - lo) * k].view(hi - lo, k)
-                L.lbimp_nn_search_ragged(s.ctx, self.dbs, s.qbuf, offsets[lo:hi + 1], [r.db for r in reqs[lo:hi]],
-                                         [r.w for r in reqs[lo:hi]], self.p, k, self.mode, idx=out_i, dist=out_d,
-                                         stats=False)
-            used = len(reqs) * self.kmax
+            out_i = s.idx.view(-1)[:used].view(len(reqs), kb)
+            out_d = s.dist.view(-1)[:used].view(len(reqs), kb)
+            L.lbimp_nn_search_ragged(s.ctx, self.dbs, s.qbuf, offsets, [r.db for r in reqs], [r.w for r in reqs],
+                                     self.p, ks, self.mode, idx=out_i, dist=out_d, stats=False)
             s.idx_h.view(-1)[:used].copy_(s.idx.view(-1)[:used], non_blocking=True)
             s.dist_h.view(-1)[:used].copy_(s.dist.view(-1)[:used], non_blocking=True)
             s.event.record(s.stream)
-        s.batch, s.classes, s.t_admit, s.busy = reqs, classes, now, True
+        s.batch, s.kb, s.t_admit, s.busy = reqs, kb, now, True
 
     def poll(self, now_fn):
         """Results of the batches that have finished (non-blocking)."""
@@ -231,14 +218,10 @@ class GpuExecutor:
                 continue
             t_done = now_fn()
             ih, dh = s.idx_h.view(-1).numpy(), s.dist_h.view(-1).numpy()
-            for k, lo, hi in s.classes:
-                base = lo * self.kmax
-                for j in range(hi - lo):
-                    r = s.batch[lo + j]
-                    a = base + j * k
-                    out.append(Result(r.rid, ih[a:a + r.k].copy(), dh[a:a + r.k].copy(), r.t_arrive, s.t_admit,
-                                      t_done))
-            s.busy, s.batch, s.classes = False, [], []
+            for j, r in enumerate(s.batch):
+                a = j * s.kb
+                out.append(Result(r.rid, ih[a:a + r.k].copy(), dh[a:a + r.k].copy(), r.t_arrive, s.t_admit, t_done))
+            s.busy, s.batch = False, []
         return out
 
     def close(self):

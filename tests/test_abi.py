@@ -69,3 +69,12 @@ def test_missing_library_fails_loudly(tmp_path):
     spec.loader.exec_module(mod)
     with pytest.raises(FileNotFoundError):
         mod.load(str(tmp_path / "nope.so"))
+
+
+def test_ragged_search_takes_one_k_per_query():
+    """lbimp_nn_search_ragged (and its workspace query) take k as a host array of Q values."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for name in ("lbimp_nn_search_ragged", "lbimp_nn_search_ragged_workspace"):
+        decl = re.search(name + r"\s*\(([^;]*)\)\s*;", text, flags=re.S).group(1)
+        params = [" ".join(a.split()) for a in decl.split(",")]
+        assert "const int32_t *k" in params, (name, params)

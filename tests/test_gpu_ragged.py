@@ -219,3 +219,27 @@ def test_ragged_uneven4096_full_size(L):
         for h in handles:
             h.close()
         ctx2.close()
+
+
+@pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
+@pytest.mark.parametrize("p", [1, 2])
+def test_ragged_per_query_k(L, ctx, dbs, mode, p):
+    """k chosen per query (1, 3, 5 or 10) in one ragged call: row q holds query q's own k nearest
+    neighbours, then -1 / +inf up to the largest k; each row equals lbimp_nn_search of that query
+    alone with its own k, bit for bit, and matches the oracle.  One group has a single k, the
+    others mix them."""
+    _say(f"ragged per-query k mode={mode} p={p}")
+    Xs, handles = dbs
+    db_of, w, Ys, offsets, packed = _mix(50 + p, 41, LENGTHS, BANDS)
+    kq = gen.rng(602, 0, p).choice(np.array([1, 3, 5, 10], np.int32), len(db_of))
+    kq[db_of == 2] = 3  # the 256-length groups share one k
+    idx, dist, st = L.lbimp_nn_search_ragged(ctx, handles, to_dev(packed), offsets, db_of, w, p, kq, mode)
+    idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+    assert idx.shape == (len(db_of), int(kq.max()))
+    for q, b in enumerate(db_of):
+        k = int(kq[q])
+        check_knn(Xs[b], Ys[q][None, :], int(w[q]), p, k, idx[q:q + 1], dist[q:q + 1], f"per-query k q={q} k={k}")
+        ai, ad, _ = L.lbimp_nn_search(ctx, handles[b], to_dev(Ys[q][None, :]), int(w[q]), p, k, mode, stats=False)
+        assert np.array_equal(idx[q, :k], ai.cpu().numpy()[0]), q
+        assert np.array_equal(dist[q, :k].view(np.uint32), ad.cpu().numpy()[0].view(np.uint32)), q
+        assert np.all(idx[q, k:] == -1) and np.all(np.isinf(dist[q, k:]))
