@@ -72,7 +72,8 @@ double orc_lb_keogh_pow(const double *x, const double *U, const double *L, int n
     return acc;
 }
 
-/* Sec. 8: LB_Improved_p(x,y)^p; scratch must hold 3n doubles. */
+/* Sec. 8: LB_Improved_p(x,y)^p; scratch must hold 3n doubles.  For p = infinity the two
+ * LB_Keogh terms combine by a maximum (Theorem 1 of Sec. 5 in its p = infinity form). */
 double orc_lb_improved_pow(const double *x, const double *y, const double *U, const double *L, int n, int w, int p,
                            double *scratch) {
     double *xp = scratch, *Up = scratch + n, *Lp = scratch + 2 * n;
@@ -81,7 +82,7 @@ double orc_lb_improved_pow(const double *x, const double *y, const double *U, co
         xp[i] = x[i] >= U[i] ? U[i] : (x[i] <= L[i] ? L[i] : x[i]);
     }
     orc_envelope(xp, n, w, Up, Lp);
-    return orc_lb_keogh_pow(x, U, L, n, p) + orc_lb_keogh_pow(y, Up, Lp, n, p);
+    return agg(orc_lb_keogh_pow(x, U, L, n, p), orc_lb_keogh_pow(y, Up, Lp, n, p), p);
 }
 
 /* Sec. 4: D(i,j) = c(i,j) + min(D(i-1,j), D(i,j-1), D(i-1,j-1)), |i-j| <= w, D(-1,-1) = 0.

@@ -177,13 +177,17 @@ def lb_improved_pow(x, y, U, L, w, p) -> float:
 
     The second term measures y against the envelope (same w) of the projection
     x' = H(x,y) of the candidate onto the envelope (U, L) of the query.
+
+    p = inf: the paper defines LB_Improved for finite p only.  Theorem 1 (Sec. 5) states
+    DTW_inf(x,y) >= max(||x - h||_inf, NDTW_inf(h,y)) for the same h, and applied again to
+    (y, h) it gives NDTW_inf(h,y) >= LB_Keogh_inf(y, h); so the bound for p = inf is the
+    maximum of the two LB_Keogh terms (the p-th-power sum becomes a maximum, as in l_inf).
     """
-    if p == INF:
-        raise ValueError("LB_Improved is defined for 1 <= p < inf only")
     x, y = _as64(x), _as64(y)
     xp = projection(x, U, L)
     Up, Lp = envelope_naive(xp, w)
-    return lb_keogh_pow(x, U, L, p) + lb_keogh_pow(y, Up, Lp, p)
+    first, second = lb_keogh_pow(x, U, L, p), lb_keogh_pow(y, Up, Lp, p)
+    return max(first, second) if p == INF else first + second
 
 
 def lb_improved(x, y, U, L, w, p) -> float:

@@ -183,18 +183,19 @@ def check_lb_chain(lb_keogh_pow, lb_improved_pow, dtw_pow, seed=6):
         x = np.cumsum(g.standard_normal(n))
         y = np.cumsum(g.standard_normal(n))
         U, L = R.envelope_naive(y, w)
-        for p in (1, 2, 3):
+        for p in PS:
             k = lb_keogh_pow(x, U, L, p)
             i = lb_improved_pow(x, y, U, L, w, p)
             d = dtw_pow(x, y, w, p)
             assert k <= i * (1 + 1e-12) + 1e-12, (n, w, p)
             assert i <= d * (1 + 1e-12) + 1e-12, (n, w, p, i, d)
             strict += i > k * (1 + 1e-9)
-            err = R._combine(np.maximum(U - y, y - L) ** p, p) ** (1.0 / p)
-            assert d ** (1.0 / p) - k ** (1.0 / p) <= err * (1 + 1e-9) + 1e-12
+            gap = np.maximum(U - y, y - L)
+            err = root(R._combine(gap if p == INF else gap ** p, p), p)
+            assert root(d, p) - root(k, p) <= err * (1 + 1e-9) + 1e-12
         U0, L0 = R.envelope_naive(y, 0)
-        for p in (1, 2):
-            lp = R._combine(np.abs(x - y) ** p, p)
+        for p in (1, 2, INF):
+            lp = R._combine(np.abs(x - y) if p == INF else np.abs(x - y) ** p, p)
             assert _rel_close(lb_keogh_pow(x, U0, L0, p), lp)
             assert _rel_close(lb_improved_pow(x, y, U0, L0, 0, p), lp)
         c = g.standard_normal()

@@ -123,8 +123,16 @@ def _lbi_dropped_term(x, y, U, L, w, p):
     return R.lb_keogh_pow(x, U, L, p)
 
 
+def _lbi_inf_sum(x, y, U, L, w, p):
+    # mistake: for p = inf the two LB_Keogh terms added, as the p-th powers are for finite p
+    xp = R.projection(x, U, L)
+    Up, Lp = R.envelope_naive(xp, w)
+    return R.lb_keogh_pow(x, U, L, p) + R.lb_keogh_pow(y, Up, Lp, p)
+
+
 @pytest.mark.parametrize("lbk,lbi", [(_lbk_swapped, R.lb_improved_pow), (R.lb_keogh_pow, _lbi_envelope_of_x),
-                                     (R.lb_keogh_pow, _lbi_wrong_operand), (R.lb_keogh_pow, _lbi_dropped_term)])
+                                     (R.lb_keogh_pow, _lbi_wrong_operand), (R.lb_keogh_pow, _lbi_dropped_term),
+                                     (R.lb_keogh_pow, _lbi_inf_sum)])
 def test_lb_mistakes_are_caught(lbk, lbi):
     with pytest.raises(AssertionError):
         P.check_lb_chain(lbk, lbi, R.dtw_pow)

@@ -124,7 +124,7 @@ def test_lb_c_matches_python():
         X = np.cumsum(g.standard_normal((7, n)), axis=1)
         y = np.cumsum(g.standard_normal(n))
         U, L = R.envelope_naive(y, w)
-        for p in (1, 2, 3):
+        for p in (1, 2, 3, math.inf):
             s1, s2 = native.lb_many(X, y, w, p)
             for c in range(7):
                 assert P._rel_close(s1[c], R.lb_keogh_pow(X[c], U, L, p), 1e-12)
