@@ -152,6 +152,21 @@ int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, in
 int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                     int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats);
 
+/* Allocation-free variant of lbimp_nn_search, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Arguments, outputs and results are those of lbimp_nn_search without stats; tuned choices
+ * recorded in the context are used, nothing is tuned.  Instead of the context's workspace the
+ * search uses a fixed scratch array of LBIMP_NOALLOC_SCRATCH_BYTES per GPU, part of the
+ * library's code object, held by each GPU the library runs on until the process ends; the call
+ * makes no hipMalloc, hipFree or other allocation.  A search that needs more scratch (it grows
+ * about as 12 Q N bytes, plus 8 Q N for k > 1) returns LBIMP_E_NOMEM before enqueueing anything.
+ * Every call on a GPU shares that GPU's array and leaves the last call's contents in it (each
+ * search clears what it needs itself): calls whose work overlaps on one GPU -- from several
+ * contexts, streams or threads -- race and give unspecified results. */
+#define LBIMP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lbimp_nn_search_noalloc(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w,
+                            int32_t p, int32_t k, int32_t mode, int64_t *idx, float *dist);
+
 /* A ragged batch: Q queries of mixed lengths, bands, databases and k in one call (the search
  * of Algorithms 2 and 3 for each query; batching changes no result).
  *   dbs       host [ndb] database handles (lengths may differ);

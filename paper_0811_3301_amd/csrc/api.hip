@@ -12,6 +12,7 @@
 #include <cstring>
 #include <iterator>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -23,6 +24,15 @@ using namespace lbimp;
 using u64 = unsigned long long;
 
 static thread_local std::string g_err;
+
+// Fixed device scratch of lbimp_nn_search_noalloc.  The library's code object holds one copy
+// per GPU it is loaded on, kept until the process ends.  In host code the array's name is not
+// a device address: the address of each GPU's copy is looked up once per device when a
+// context is created there, and only that address is used afterwards.
+static __device__ __align__(256) unsigned char scratch[LBIMP_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
 
 static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 static int fail(int code, const char *fmt, ...) {
@@ -143,6 +153,19 @@ static int reserve(lbimp_ctx *ctx, size_t bytes) {
         return fail(LBIMP_E_NOMEM, "workspace allocation of %zu bytes failed", cap);
     }
     ctx->ws_cap = cap;
+    return LBIMP_OK;
+}
+
+// Address of this device's copy of `scratch` (the device must be current).
+static int init_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(LBIMP_E_UNSUPPORTED, "device %d: at most %d devices", device,
+                                                         kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return LBIMP_OK;
+    void *ptr = nullptr;
+    HIPTRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(LBIMP_E_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[device] = ptr;
     return LBIMP_OK;
 }
 
@@ -662,6 +685,10 @@ int lbimp_ctx_create(int device, void *hip_stream, lbimp_ctx **out) {
     if (!ctx) return fail(LBIMP_E_NOMEM, "host allocation failed");
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    if (int r = init_scratch(device)) {
+        delete ctx;
+        return r;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cu = prop.multiProcessorCount;
     *out = ctx;
@@ -950,6 +977,35 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
         HIPTRY(hipStreamSynchronize(ctx->stream));
         fill_stats(d, Q, h.data(), nullptr, stats);
     }
+    return LBIMP_OK;
+}
+
+int lbimp_nn_search_noalloc(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
+                            int32_t k, int32_t mode, int64_t *idx, float *dist) {
+    if (int r = check_ctx(ctx)) return r;
+    if (!db) return fail(LBIMP_E_INVALID, "null database");
+    if (db->device != ctx->device) return fail(LBIMP_E_INVALID, "database lives on another device");
+    if (int r = check_search(Q, db->n, w, p, k, mode)) return r;
+    if (Q == 0) return LBIMP_OK;
+    if (!queries || !idx || !dist) return fail(LBIMP_E_INVALID, "null pointer");
+    void *base = g_scratch_ptr[ctx->device];
+    if (!base) return fail(LBIMP_E_DEVICE, "scratch of device %d not initialised", ctx->device);
+    // tuned choices are used when present; nothing is tuned here (tuning needs a workspace)
+    const int wb = band_of(db->n, w);
+    SearchSpec sp{db, queries, Q, w, p, k, mode, idx, dist, nullptr, knobs_for(ctx, db, Q, wb, p, k, mode)};
+    SearchDims d;
+    if (int r = dims_of(sp, ctx->num_cu, d)) return r;
+    SearchBufs bufs;
+    Carver cv{nullptr};
+    layout(cv, d, bufs);
+    if (cv.off > (size_t)LBIMP_NOALLOC_SCRATCH_BYTES)
+        return fail(LBIMP_E_NOMEM, "search needs %zu bytes of scratch, more than the fixed %zu (LBIMP_NOALLOC_SCRATCH_BYTES)",
+                    cv.off, (size_t)LBIMP_NOALLOC_SCRATCH_BYTES);
+    Carver c2{static_cast<char *>(base)};
+    layout(c2, d, bufs);
+    ctx->timed_valid = false;
+    if (int r = enqueue_search(ctx, sp, d, bufs, ctx->stream, true)) return r;
+    ctx->timed_valid = ctx->timing;
     return LBIMP_OK;
 }
 

@@ -53,6 +53,7 @@ SIGNATURES = {
     "lbimp_dtw_band": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _i32, _i32, _vp]),
     "lbimp_nn_search": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp,
                                        ctypes.POINTER(LbimpStats)]),
+    "lbimp_nn_search_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp]),
     "lbimp_nn_search_ragged": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i32, _vp, ctypes.POINTER(_i64),
                                               ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i64, _i32,
                                               ctypes.POINTER(_i32), _i32, _vp, _vp, ctypes.POINTER(LbimpStats)]),
@@ -247,6 +248,21 @@ def lbimp_nn_search(ctx: Ctx, db: Db, queries: torch.Tensor, w: int, p: int, k: 
     _check(_lib.lbimp_nn_search(ctx.sync_stream(), db.h, _dev(queries, "queries") if Q else None, Q, w, p, k, mode,
                                 _dev(idx, "idx", torch.int64), _dev(dist, "dist"), st), "lbimp_nn_search")
     return idx, dist, (_stats_array(st, Q) if stats else None)
+
+
+def lbimp_nn_search_noalloc(ctx: Ctx, db: Db, queries: torch.Tensor, w: int, p: int, k: int = 1, mode="improved",
+                            idx=None, dist=None):
+    """lbimp_nn_search on the library's fixed device scratch (no allocation inside the call).
+    Returns (idx [Q][k] int64, dist [Q][k] float32)."""
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    Q = queries.shape[0]
+    idx = _out(idx, (Q, k), torch.int64, queries)
+    dist = _out(dist, (Q, k), torch.float32, queries)
+    _check(_lib.lbimp_nn_search_noalloc(ctx.sync_stream(), db.h, _dev(queries, "queries") if Q else None, Q, w, p,
+                                        k, mode, _dev(idx, "idx", torch.int64), _dev(dist, "dist")),
+           "lbimp_nn_search_noalloc")
+    return idx, dist
 
 
 def _stats_array(st, Q):
