@@ -14,9 +14,12 @@
  *     The library never frees caller memory.  Pointers marked "host" are host memory.
  *   - Calls enqueue work on the context's stream and return without waiting, except
  *     where a host output is written (stats, stage times), which waits for the stream.
- *   - p is the exponent of DTW_p and of the bounds: 1 or 2 (other values return
- *     LBIMP_E_UNSUPPORTED).  All distances returned are in root form (DTW_p,
- *     LB_Keogh_p, LB_Improved_p), computed in float32.
+ *   - p is the exponent of DTW_p and of the bounds: 1, 2 or LBIMP_P_INF (p = infinity,
+ *     where every sum of p-th powers becomes a maximum: DTW_inf by the Sec. 4 recursion
+ *     with max for +, LB_Keogh_inf of Sec. 7, and LB_Improved_inf = max(LB_Keogh_inf(x,y),
+ *     LB_Keogh_inf(y, H(x,y))), the p = infinity form of Theorem 1 in Sec. 5; other values
+ *     return LBIMP_E_UNSUPPORTED, p < 1 LBIMP_E_INVALID).  All distances returned are in
+ *     root form (DTW_p, LB_Keogh_p, LB_Improved_p), computed in float32.
  *   - w is the locality constraint |i - j| <= w (Sec. 4), w >= 0; w >= n is the
  *     unconstrained DTW and behaves as w = n - 1.
  *   - Inputs must be finite; non-finite values give unspecified results.
@@ -35,13 +38,14 @@ extern "C" {
 #endif
 
 #define LBIMP_MAX_LEN 4096
+#define LBIMP_P_INF 0x7fffffff /* the exponent p = infinity */
 
 enum {
     LBIMP_OK = 0,
     LBIMP_E_INVALID = 1,     /* bad argument: null pointer, n < 1, n > LBIMP_MAX_LEN, w < 0, k < 1, ... */
     LBIMP_E_NOMEM = 2,       /* device or host allocation failed */
     LBIMP_E_DEVICE = 3,      /* a HIP runtime call failed */
-    LBIMP_E_UNSUPPORTED = 4  /* valid request outside what is implemented (p other than 1 or 2) */
+    LBIMP_E_UNSUPPORTED = 4  /* valid request outside what is implemented (p other than 1, 2, infinity) */
 };
 
 enum {

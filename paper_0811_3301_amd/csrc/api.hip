@@ -180,7 +180,8 @@ static int check_shape(int64_t count, int32_t n, int32_t w, int32_t p) {
     if (n < 1 || n > LBIMP_MAX_LEN) return fail(LBIMP_E_INVALID, "series length %d outside [1, %d]", n, LBIMP_MAX_LEN);
     if (w < 0) return fail(LBIMP_E_INVALID, "locality constraint w = %d < 0", w);
     if (p < 1) return fail(LBIMP_E_INVALID, "exponent p = %d < 1", p);
-    if (p > 2) return fail(LBIMP_E_UNSUPPORTED, "exponent p = %d: only p = 1 and p = 2 are implemented", p);
+    if (p > 2 && p != LBIMP_P_INF)
+        return fail(LBIMP_E_UNSUPPORTED, "exponent p = %d: p = 1, p = 2 and p = infinity are implemented", p);
     if (count > INT32_MAX) return fail(LBIMP_E_INVALID, "more than 2^31-1 series");
     return LBIMP_OK;
 }

@@ -11,14 +11,6 @@ __device__ __forceinline__ u64 make_key(float v, int c) {
     return ((u64)__float_as_uint(v) << 32) | (u64)(unsigned)c;
 }
 
-template <int P>
-__device__ __forceinline__ float root_p(float v) {
-    if constexpr (P == 1)
-        return v;
-    else
-        return sqrtf(v);
-}
-
 // Persistent work loop.  Items (a query and a batch of its pairs) are dealt to the one-wave
 // blocks of the grid in a fixed stride -- block g takes items g, g + grid, g + 2*grid, ... --
 // so no shared counter is contended.  With a fixed pair count per query the item maps to its
@@ -182,8 +174,7 @@ __host__ __device__ inline float cascade_shrink(int n) { return 1.f - (3.f * n +
 // LB_Keogh^p term of one element against the envelope [lo, hi].
 template <int P>
 __device__ __forceinline__ float lbk_term(float x, float lo, float hi) {
-    const float d = x - __builtin_amdgcn_fmed3f(x, lo, hi);
-    return (P == 1) ? fabsf(d) : d * d;
+    return pacc<P>(0.f, x - __builtin_amdgcn_fmed3f(x, lo, hi));
 }
 
 // Arguments of the register-state LB_Improved kernels (one instantiation per half-width).
@@ -212,6 +203,7 @@ hipError_t launch_lbi_wave(int p, int w, int num_cu, const LbiArgs &a, hipStream
 
 hipError_t launch_lbi_reg_p1(int w, int num_cu, const LbiArgs &a, hipStream_t s);
 hipError_t launch_lbi_reg_p2(int w, int num_cu, const LbiArgs &a, hipStream_t s);
+hipError_t launch_lbi_reg_pinf(int w, int num_cu, const LbiArgs &a, hipStream_t s);
 
 // Group-of-lanes-per-pair DTW (anti-diagonals in registers); batch = dtw_wave_batch(n, w).
 int dtw_wave_batch(int n, int w);
@@ -227,5 +219,6 @@ hipError_t launch_dtw_strip(int p, int w, int num_cu, const DtwArgs &a, float *r
 
 hipError_t launch_dtw_lane_p1(int w, int num_cu, const DtwArgs &a, hipStream_t s);
 hipError_t launch_dtw_lane_p2(int w, int num_cu, const DtwArgs &a, hipStream_t s);
+hipError_t launch_dtw_lane_pinf(int w, int num_cu, const DtwArgs &a, hipStream_t s);
 
 }  // namespace lbimp

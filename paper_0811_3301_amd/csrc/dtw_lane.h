@@ -28,7 +28,7 @@ __device__ __forceinline__ void dtw_row(float (&D)[2 * W + 1], float xi, const f
         const float up = (k + 1 < BW) ? D[k + 1] : kInf;
         const float left = (k > 0) ? D[k - 1] : kInf;
         const float m = __builtin_fminf(__builtin_fminf(D[k], up), left);
-        D[k] = (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
+        D[k] = pacc<P>(m, d);
     }
 }
 
@@ -51,7 +51,7 @@ __device__ __forceinline__ void dtw_rowsR(float (&D)[2 * W + 1], const float (&x
                 const float up = (k + 1 < BW) ? D[k + 1] : kInf;
                 const float left = (k > 0) ? D[k - 1] : kInf;
                 const float m = __builtin_fminf(__builtin_fminf(D[k], up), left);
-                D[k] = (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
+                D[k] = pacc<P>(m, d);
             }
         }
     }
@@ -155,13 +155,17 @@ static void dtw_lane_launch(int num_cu, const DtwArgs &a_in, hipStream_t s) {
         return sizeof(float) * ((size_t)a.n + 2 * W + 1 + lane_rows(W) + (cascade ? 2 * (size_t)a.n : 0));
     };
     if (a.S1 && lds_of(true) > kLdsBudget) a.S1 = nullptr;  // no room for U, L: row minimum only
+    if constexpr (P == kPInf) a.S1 = nullptr;               // the LB_Keogh tail bound sums p-th powers
     const size_t lds = lds_of(a.S1 != nullptr);
-    if (a.S1)
-        hipLaunchKernelGGL((k_dtw_lane<P, W, true>), dim3(persistent_grid(k_dtw_lane<P, W, true>, lds, num_cu)),
-                           dim3(64), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_dtw_lane<P, W, false>), dim3(persistent_grid(k_dtw_lane<P, W, false>, lds, num_cu)),
-                           dim3(64), lds, s, a);
+    if constexpr (P != kPInf) {
+        if (a.S1) {
+            hipLaunchKernelGGL((k_dtw_lane<P, W, true>), dim3(persistent_grid(k_dtw_lane<P, W, true>, lds, num_cu)),
+                               dim3(64), lds, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_dtw_lane<P, W, false>), dim3(persistent_grid(k_dtw_lane<P, W, false>, lds, num_cu)),
+                       dim3(64), lds, s, a);
 }
 
 using DtwLaneFn = void (*)(int, const DtwArgs &, hipStream_t);

@@ -54,7 +54,7 @@ __device__ __forceinline__ void strip_cols4(float (&R)[C], const float (&X)[C], 
             const float up = (r == 0) ? tc[t] : ((PH == kRight && r == u) ? kInf : R[r - 1]);
             const float m = __builtin_fminf(__builtin_fminf(left, up), dg[t]);
             const float d = X[r] - yv[t];
-            const float v = (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
+            const float v = pacc<P>(m, d);
             R[r] = v;
             dg[t] = left;
             if (r == C - 1) out[t] = v;
@@ -80,7 +80,7 @@ __device__ __forceinline__ float strip_col1(float (&R)[C], const float (&X)[C], 
         const float left = R[r];
         const float m = __builtin_fminf(__builtin_fminf(left, up), dg);
         const float d = X[r] - y;
-        const float v = (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
+        const float v = pacc<P>(m, d);
         R[r] = v;
         dg = left;
         up = v;
@@ -284,9 +284,13 @@ static int strip_grid(int n, int w, int num_cu) {
     return persistent_grid(k_dtw_strip<P, kStripRows, false>, strip_lds(n, w), num_cu);
 }
 
+static int strip_grid_p(int p, int n, int w, int num_cu) {
+    return p == 1 ? strip_grid<1>(n, w, num_cu) : p == 2 ? strip_grid<2>(n, w, num_cu) : strip_grid<kPInf>(n, w, num_cu);
+}
+
 size_t dtw_strip_scratch(int p, int n, int w, int num_cu) {
     if (w <= kLaneMaxW) return 0;
-    const int grid = p == 1 ? strip_grid<1>(n, w, num_cu) : strip_grid<2>(n, w, num_cu);
+    const int grid = strip_grid_p(p, n, w, num_cu);
     return sizeof(float) * (size_t)grid * ((size_t)1 << ring_log2(w)) * 64;
 }
 
@@ -301,7 +305,7 @@ hipError_t launch_dtw_strip(int p, int w, int num_cu, const DtwArgs &a_in, float
     const int rl = ring_log2(w);
     // the ring was sized for the grid of the plain kernel without U, L in LDS; the grid launched
     // here is capped to it
-    const int cap = p == 1 ? strip_grid<1>(a.n, w, num_cu) : strip_grid<2>(a.n, w, num_cu);
+    const int cap = strip_grid_p(p, a.n, w, num_cu);
 #define LBIMP_STRIP(PP, CC)                                                                                         \
     hipLaunchKernelGGL((k_dtw_strip<PP, kStripRows, CC>),                                                          \
                        dim3(std::min(cap, persistent_grid(k_dtw_strip<PP, kStripRows, CC>, lds, num_cu))), dim3(64), \
@@ -310,9 +314,12 @@ hipError_t launch_dtw_strip(int p, int w, int num_cu, const DtwArgs &a_in, float
     if (p == 1) {
         if (cas) LBIMP_STRIP(1, true);
         else LBIMP_STRIP(1, false);
-    } else {
+    } else if (p == 2) {
         if (cas) LBIMP_STRIP(2, true);
         else LBIMP_STRIP(2, false);
+    } else {
+        if (cas) return hipErrorInvalidValue;  // the LB_Keogh tail bound sums p-th powers
+        LBIMP_STRIP(kPInf, false);
     }
 #undef LBIMP_STRIP
     return hipGetLastError();

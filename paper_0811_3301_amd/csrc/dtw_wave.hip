@@ -36,7 +36,7 @@ __device__ __forceinline__ float dpp_shl1(float v) {  // lane l gets lane l+1, l
 
 template <int P>
 __device__ __forceinline__ float cost_add(float d, float m) {
-    return (P == 1) ? m + fabsf(d) : fmaf(d, d, m);
+    return pacc<P>(m, d);
 }
 
 template <int P>
@@ -264,10 +264,14 @@ hipError_t launch_dtw_wavereg_wide(int p, int w, int num_cu, const DtwArgs &a, h
         if (r == 2) LBIMP_WAVE_R(1, 2);
         else if (r == 4) LBIMP_WAVE_R(1, 4);
         else LBIMP_WAVE_R(1, 8);
-    } else {
+    } else if (p == 2) {
         if (r == 2) LBIMP_WAVE_R(2, 2);
         else if (r == 4) LBIMP_WAVE_R(2, 4);
         else LBIMP_WAVE_R(2, 8);
+    } else {
+        if (r == 2) LBIMP_WAVE_R(kPInf, 2);
+        else if (r == 4) LBIMP_WAVE_R(kPInf, 4);
+        else LBIMP_WAVE_R(kPInf, 8);
     }
 #undef LBIMP_WAVE_R
     return hipGetLastError();
@@ -288,12 +292,15 @@ hipError_t launch_dtw_wavereg(int p, int w, int num_cu, const DtwArgs &a, hipStr
     const int LP = wave_lanes(a.n, w);
     const size_t lds = sizeof(float) * (size_t)(a.n + 2 * kWavePad) * (1 + 64 / LP);
     if (lds > kLdsBudget) return hipErrorInvalidValue;
+#define LBIMP_WAVEREG(PP) \
+    hipLaunchKernelGGL(k_dtw_wavereg<PP>, dim3(persistent_grid(k_dtw_wavereg<PP>, lds, num_cu)), dim3(64), lds, s, a, w, LP)
     if (p == 1)
-        hipLaunchKernelGGL(k_dtw_wavereg<1>, dim3(persistent_grid(k_dtw_wavereg<1>, lds, num_cu)), dim3(64), lds, s,
-                           a, w, LP);
+        LBIMP_WAVEREG(1);
+    else if (p == 2)
+        LBIMP_WAVEREG(2);
     else
-        hipLaunchKernelGGL(k_dtw_wavereg<2>, dim3(persistent_grid(k_dtw_wavereg<2>, lds, num_cu)), dim3(64), lds, s,
-                           a, w, LP);
+        LBIMP_WAVEREG(kPInf);
+#undef LBIMP_WAVEREG
     return hipGetLastError();
 }
 

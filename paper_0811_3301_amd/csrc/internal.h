@@ -6,6 +6,7 @@
 #include <cstdint>
 
 #include "lbimp.h"
+#include "pnorm.h"
 
 namespace lbimp {
 

@@ -28,11 +28,7 @@ int lbi_batch(int n, int w) {
 
 template <int P>
 __device__ __forceinline__ float lb_acc(float acc, float v, float lo, float hi) {
-    float d = v - __builtin_amdgcn_fmed3f(v, lo, hi);
-    if constexpr (P == 1)
-        return acc + fabsf(d);
-    else
-        return fmaf(d, d, acc);
+    return pacc<P>(acc, v - __builtin_amdgcn_fmed3f(v, lo, hi));
 }
 
 template <int P>
@@ -108,7 +104,7 @@ __global__ __launch_bounds__(64) void k_lbi(const float *__restrict__ rows, int 
                 }
             }
         }
-        const float s2 = (active ? S1[q * ldS + c] : 0.f) + acc;
+        const float s2 = pjoin<P>(active ? S1[q * ldS + c] : 0.f, acc);
         if (out_root && active) out_root[c] = root_p<P>(s2);
         if (thr) {
             const bool keep = active && make_key(s2, c) < thr[q];
@@ -130,17 +126,22 @@ hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, 
     if (w <= kLbiRegMaxW || lbi_wave_supported(n, w)) {
         LbiArgs a{rows, db_bytes, n, qd, pl, S1, ldS, prefix, Q, ctr, thr, list2, ldl2, cnt2, out_root, pipeline};
         if (w > kLbiRegMaxW) return launch_lbi_wave(p, w, num_cu, a, s);
-        return p == 1 ? launch_lbi_reg_p1(w, num_cu, a, s) : launch_lbi_reg_p2(w, num_cu, a, s);
+        if (p == 1) return launch_lbi_reg_p1(w, num_cu, a, s);
+        return p == 2 ? launch_lbi_reg_p2(w, num_cu, a, s) : launch_lbi_reg_pinf(w, num_cu, a, s);
     }
     const int WL = lbi_batch(n, w);
     const int K = 2 * w + 1;
     size_t lds = sizeof(float) * (3 * (size_t)n + 2 * (size_t)(K + 1) * WL);
+#define LBIMP_LBI(PP)                                                                                             \
+    hipLaunchKernelGGL(k_lbi<PP>, dim3(persistent_grid(k_lbi<PP>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, \
+                       S1, ldS, prefix, Q, ctr, WL, thr, list2, ldl2, cnt2, out_root)
     if (p == 1)
-        hipLaunchKernelGGL(k_lbi<1>, dim3(persistent_grid(k_lbi<1>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, S1, ldS, prefix, Q, ctr, WL,
-                           thr, list2, ldl2, cnt2, out_root);
+        LBIMP_LBI(1);
+    else if (p == 2)
+        LBIMP_LBI(2);
     else
-        hipLaunchKernelGGL(k_lbi<2>, dim3(persistent_grid(k_lbi<2>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, S1, ldS, prefix, Q, ctr, WL,
-                           thr, list2, ldl2, cnt2, out_root);
+        LBIMP_LBI(kPInf);
+#undef LBIMP_LBI
     return hipGetLastError();
 }
 
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(64) void k_dtw_wave(const float *__restrict__ rows,
             for (int i = lo + lane; i <= hi; i += 64) {
                 const float dd = sx[i] - sy[d - i];
                 const float m = fminf(fminf(Bm[i], Bm[i + 1]), Am[i]);
-                const float v = (P == 1) ? m + fabsf(dd) : fmaf(dd, dd, m);
+                const float v = pacc<P>(m, dd);
                 C[i + 1] = v;
                 mcur = fminf(mcur, v);
             }
@@ -232,19 +233,24 @@ hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, Pair
         const u64 *tkeys = best ? best : thr;
         if (!tkeys) return hipErrorInvalidValue;  // callers pass a threshold array, kNoKey-filled if unused
         DtwArgs a{rows, n, qd, pl, prefix, Q, ctr, best, thr, res, ldres, rescnt, abandoned, out_root, abandon, tkeys,
-                  abandon ? S1 : nullptr, ldS};
+                  abandon && p != kPInf ? S1 : nullptr, ldS};  // the LB_Keogh tail bound sums p-th powers
         if (w > kLaneMaxW && low_latency) return launch_dtw_wavereg_wide(p, w, num_cu, a, s);
         if (w > kLaneMaxW) return launch_dtw_strip(p, w, num_cu, a, ring, ring_bytes, s);
         if (low_latency) return launch_dtw_wavereg(p, w, num_cu, a, s);
-        return p == 1 ? launch_dtw_lane_p1(w, num_cu, a, s) : launch_dtw_lane_p2(w, num_cu, a, s);
+        if (p == 1) return launch_dtw_lane_p1(w, num_cu, a, s);
+        return p == 2 ? launch_dtw_lane_p2(w, num_cu, a, s) : launch_dtw_lane_pinf(w, num_cu, a, s);
     }
     const size_t lds = sizeof(float) * (3 * (size_t)n + 3);
+#define LBIMP_DTW_WAVE(PP)                                                                                          \
+    hipLaunchKernelGGL(k_dtw_wave<PP>, dim3(persistent_grid(k_dtw_wave<PP>, lds, num_cu)), dim3(64), lds, s, rows, n, w, \
+                       qd, pl, prefix, Q, ctr, best, thr, res, ldres, rescnt, abandoned, out_root, abandon)
     if (p == 1)
-        hipLaunchKernelGGL(k_dtw_wave<1>, dim3(persistent_grid(k_dtw_wave<1>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, prefix, Q, ctr, best, thr,
-                           res, ldres, rescnt, abandoned, out_root, abandon);
+        LBIMP_DTW_WAVE(1);
+    else if (p == 2)
+        LBIMP_DTW_WAVE(2);
     else
-        hipLaunchKernelGGL(k_dtw_wave<2>, dim3(persistent_grid(k_dtw_wave<2>, lds, num_cu)), dim3(64), lds, s, rows, n, w, qd, pl, prefix, Q, ctr, best, thr,
-                           res, ldres, rescnt, abandoned, out_root, abandon);
+        LBIMP_DTW_WAVE(kPInf);
+#undef LBIMP_DTW_WAVE
     return hipGetLastError();
 }
 
@@ -288,7 +294,7 @@ hipError_t launch_kth_key(const unsigned long long *res, int64_t ldres, const in
 
 __device__ __forceinline__ float key_root(u64 key, int p) {
     float v = __uint_as_float((unsigned)(key >> 32));
-    return p == 1 ? v : sqrtf(v);
+    return p == 2 ? sqrtf(v) : v;
 }
 
 // Output row r holds ldo entries: the best key in entry 0, -1 / +inf in the others.

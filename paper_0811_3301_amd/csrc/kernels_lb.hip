@@ -174,19 +174,7 @@ hipError_t launch_pad_env(const float *U, const float *L, int64_t B, int64_t Bpa
 // d(x, [L, U]) = x - med3(x, L, U): zero inside the envelope, x - U above, x - L below.
 template <int P>
 __device__ __forceinline__ float lb_term(float acc, float x, float l, float u) {
-    float d = x - __builtin_amdgcn_fmed3f(x, l, u);
-    if constexpr (P == 1)
-        return acc + fabsf(d);
-    else
-        return fmaf(d, d, acc);
-}
-
-template <int P>
-__device__ __forceinline__ float root_p(float v) {
-    if constexpr (P == 1)
-        return v;
-    else
-        return sqrtf(v);
+    return pacc<P>(acc, x - __builtin_amdgcn_fmed3f(x, l, u));
 }
 
 // Block = 4 waves; wave -> CPL consecutive tiles (lane = candidate), block.y -> QG queries.
@@ -370,8 +358,11 @@ hipError_t launch_lbk_sweep(int p, int shape, const float4 *il, int64_t N, int n
     if (p == 1)
         return root ? sweep_p<1, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
                     : sweep_p<1, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
-    return root ? sweep_p<2, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
-                : sweep_p<2, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+    if (p == 2)
+        return root ? sweep_p<2, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
+                    : sweep_p<2, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+    // p = infinity: LB_Keogh_inf is its own root form
+    return sweep_p<kPInf, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
 }
 
 // ------------------------------------------------------------------ seed selection

@@ -40,7 +40,7 @@ __device__ __forceinline__ void lbi_forward(float &acc, const float (&hx)[2 * W 
                 const float lm = fminf(hn[o + 1], gn);
                 const float yv = yb[o - W];
                 const float d = yv - __builtin_amdgcn_fmed3f(yv, lm, um);
-                acc = (P == 1) ? acc + fabsf(d) : fmaf(d, d, acc);
+                acc = pacc<P>(acc, d);
             }
         }
     }
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
                 }
             }
         }
-        const float s2 = (active ? a.S1[q * a.ldS + c] : 0.f) + acc;
+        const float s2 = pjoin<P>(active ? a.S1[q * a.ldS + c] : 0.f, acc);
         if (a.out_root && active) a.out_root[c] = root_p<P>(s2);
         if (a.thr) {
             const bool keep = active && make_key(s2, c) < a.thr[q];

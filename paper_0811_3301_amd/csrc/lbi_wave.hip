@@ -113,7 +113,7 @@ __device__ __forceinline__ float lbi_pass(const float (&xraw)[M], const float (&
         const float e = op(j >= hfrom ? sh[ah] : kNeutral, sg[ag]);
         float d = MAX ? fmaxf(yv[j] - e, 0.f) : fmaxf(e - yv[j], 0.f);
         d = j < valid ? d : 0.f;
-        acc = (P == 1) ? acc + d : fmaf(d, d, acc);
+        acc = pacc<P>(acc, d);
         if (++rg == M) rg = 0, ++qg;
         if (++rh == M) rh = 0, ++qh;
     }
@@ -172,13 +172,13 @@ __global__ __launch_bounds__(64) void k_lbi_wave(LbiArgs a, int w) {
                 xp[j] = __builtin_amdgcn_fmed3f(xr[j], sLq[j * 64 + lane], sUq[j * 64 + lane]);
             if (t + 1 < cnt) load_row(t + 1);
             float acc = lbi_pass<P, M, true>(xp, yv, sg, sh, w, n, lane, rj);
-            acc += lbi_pass<P, M, false>(xp, yv, sg, sh, w, n, lane, rj);
+            acc = pjoin<P>(acc, lbi_pass<P, M, false>(xp, yv, sg, sh, w, n, lane, rj));
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            for (int off = 32; off > 0; off >>= 1) acc = pjoin<P>(acc, __shfl_xor(acc, off));
             if (lane == t) s2_mine = acc;
         }
         const bool active = lane < cnt;
-        const float s2 = (active ? a.S1[q * a.ldS + c_mine] : 0.f) + s2_mine;
+        const float s2 = pjoin<P>(active ? a.S1[q * a.ldS + c_mine] : 0.f, s2_mine);
         if (a.out_root && active) a.out_root[c_mine] = root_p<P>(s2);
         if (a.thr) {
             const bool keep = active && make_key(s2, c_mine) < a.thr[q];
@@ -232,7 +232,9 @@ static hipError_t lbi_wave_dispatch(int m, int w, int num_cu, const LbiArgs &a, 
 hipError_t launch_lbi_wave(int p, int w, int num_cu, const LbiArgs &a, hipStream_t s) {
     if (!lbi_wave_supported(a.n, w)) return hipErrorInvalidValue;
     const int m = lbi_wave_m(a.n, w);
-    return p == 1 ? lbi_wave_dispatch<1>(m, w, num_cu, a, s) : lbi_wave_dispatch<2>(m, w, num_cu, a, s);
+    if (p == 1) return lbi_wave_dispatch<1>(m, w, num_cu, a, s);
+    if (p == 2) return lbi_wave_dispatch<2>(m, w, num_cu, a, s);
+    return lbi_wave_dispatch<kPInf>(m, w, num_cu, a, s);
 }
 
 }  // namespace lbimp

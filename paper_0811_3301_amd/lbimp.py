@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbimp.so")
 
 LBIMP_OK, LBIMP_E_INVALID, LBIMP_E_NOMEM, LBIMP_E_DEVICE, LBIMP_E_UNSUPPORTED = 0, 1, 2, 3, 4
 LBIMP_MODE_BRUTE, LBIMP_MODE_KEOGH, LBIMP_MODE_IMPROVED = 0, 1, 2
+LBIMP_P_INF = 0x7FFFFFFF  # the exponent p = infinity
 MODES = {"brute": LBIMP_MODE_BRUTE, "keogh": LBIMP_MODE_KEOGH, "improved": LBIMP_MODE_IMPROVED}
 STAGES = ("envelope", "lb_keogh", "select_seeds", "seed_dtw", "compact", "lb_improved", "dtw", "finalize")
 
@@ -105,6 +106,11 @@ def _dev(t: torch.Tensor, name: str, dtype=torch.float32) -> int:
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t.data_ptr()
+
+
+def _p(p) -> int:
+    """The exponent as the C-ABI takes it: math.inf (or LBIMP_P_INF) selects p = infinity."""
+    return LBIMP_P_INF if p == float("inf") else int(p)
 
 
 def _stream() -> int:
@@ -205,7 +211,7 @@ def lbimp_envelope(ctx: Ctx, y: torch.Tensor, w: int, U=None, L=None):
 def lbimp_lb_keogh(ctx: Ctx, x: torch.Tensor, U: torch.Tensor, L: torch.Tensor, p: int, out=None):
     N, n = x.shape
     out = _out(out, (N,), torch.float32, x)
-    _check(_lib.lbimp_lb_keogh(ctx.sync_stream(), _dev(x, "x"), N, n, _dev(U, "U"), _dev(L, "L"), p,
+    _check(_lib.lbimp_lb_keogh(ctx.sync_stream(), _dev(x, "x"), N, n, _dev(U, "U"), _dev(L, "L"), _p(p),
                                _dev(out, "lb")), "lbimp_lb_keogh")
     return out
 
@@ -214,7 +220,7 @@ def lbimp_db_lb_keogh(ctx: Ctx, db: Db, U: torch.Tensor, L: torch.Tensor, p: int
     U2 = U.reshape(-1, db.n)
     Q = U2.shape[0]
     out = _out(out, (Q, db.N), torch.float32, U)
-    _check(_lib.lbimp_db_lb_keogh(ctx.sync_stream(), db.h, _dev(U2, "U"), _dev(L.reshape(-1, db.n), "L"), Q, p,
+    _check(_lib.lbimp_db_lb_keogh(ctx.sync_stream(), db.h, _dev(U2, "U"), _dev(L.reshape(-1, db.n), "L"), Q, _p(p),
                                   _dev(out, "lb")), "lbimp_db_lb_keogh")
     return out
 
@@ -224,14 +230,14 @@ def lbimp_lb_improved(ctx: Ctx, x: torch.Tensor, y: torch.Tensor, U: torch.Tenso
     N, n = x.shape
     out = _out(out, (N,), torch.float32, x)
     _check(_lib.lbimp_lb_improved(ctx.sync_stream(), _dev(x, "x"), N, n, _dev(y, "y"), _dev(U, "U"), _dev(L, "L"),
-                                  w, p, _dev(out, "lb")), "lbimp_lb_improved")
+                                  w, _p(p), _dev(out, "lb")), "lbimp_lb_improved")
     return out
 
 
 def lbimp_dtw_band(ctx: Ctx, x: torch.Tensor, y: torch.Tensor, w: int, p: int, out=None):
     N, n = x.shape
     out = _out(out, (N,), torch.float32, x)
-    _check(_lib.lbimp_dtw_band(ctx.sync_stream(), _dev(x, "x"), N, _dev(y, "y"), n, w, p, _dev(out, "dist")),
+    _check(_lib.lbimp_dtw_band(ctx.sync_stream(), _dev(x, "x"), N, _dev(y, "y"), n, w, _p(p), _dev(out, "dist")),
            "lbimp_dtw_band")
     return out
 
@@ -245,7 +251,7 @@ def lbimp_nn_search(ctx: Ctx, db: Db, queries: torch.Tensor, w: int, p: int, k: 
     idx = _out(idx, (Q, k), torch.int64, queries)
     dist = _out(dist, (Q, k), torch.float32, queries)
     st = (LbimpStats * max(Q, 1))() if stats else None
-    _check(_lib.lbimp_nn_search(ctx.sync_stream(), db.h, _dev(queries, "queries") if Q else None, Q, w, p, k, mode,
+    _check(_lib.lbimp_nn_search(ctx.sync_stream(), db.h, _dev(queries, "queries") if Q else None, Q, w, _p(p), k, mode,
                                 _dev(idx, "idx", torch.int64), _dev(dist, "dist"), st), "lbimp_nn_search")
     return idx, dist, (_stats_array(st, Q) if stats else None)
 
@@ -259,7 +265,7 @@ def lbimp_nn_search_noalloc(ctx: Ctx, db: Db, queries: torch.Tensor, w: int, p: 
     Q = queries.shape[0]
     idx = _out(idx, (Q, k), torch.int64, queries)
     dist = _out(dist, (Q, k), torch.float32, queries)
-    _check(_lib.lbimp_nn_search_noalloc(ctx.sync_stream(), db.h, _dev(queries, "queries") if Q else None, Q, w, p,
+    _check(_lib.lbimp_nn_search_noalloc(ctx.sync_stream(), db.h, _dev(queries, "queries") if Q else None, Q, w, _p(p),
                                         k, mode, _dev(idx, "idx", torch.int64), _dev(dist, "dist")),
            "lbimp_nn_search_noalloc")
     return idx, dist
@@ -302,7 +308,7 @@ def lbimp_nn_search_ragged(ctx: Ctx, dbs, queries: torch.Tensor, offsets, db_of,
     _check(_lib.lbimp_nn_search_ragged(
         ctx.sync_stream(), handles, len(dbs), _dev(queries, "queries") if queries.numel() else None,
         off.ctypes.data_as(ctypes.POINTER(_i64)), dof.ctypes.data_as(ctypes.POINTER(_i32)),
-        wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p, kq.ctypes.data_as(ctypes.POINTER(_i32)), mode,
+        wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, _p(p), kq.ctypes.data_as(ctypes.POINTER(_i32)), mode,
         _dev(idx, "idx", torch.int64), _dev(dist, "dist"), st), "lbimp_nn_search_ragged")
     return idx, dist, (_stats_array(st, Q) if stats else None)
 
@@ -318,7 +324,7 @@ def lbimp_nn_search_ragged_workspace(ctx: Ctx, dbs, db_of, w, p: int, k=1, mode=
     handles = (_vp * max(len(dbs), 1))(*[d.h for d in dbs])
     out = ctypes.c_uint64(0)
     _check(_lib.lbimp_nn_search_ragged_workspace(ctx.h, handles, len(dbs), dof.ctypes.data_as(ctypes.POINTER(_i32)),
-                                                 wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, p,
+                                                 wq.ctypes.data_as(ctypes.POINTER(_i32)), Q, _p(p),
                                                  kq.ctypes.data_as(ctypes.POINTER(_i32)), mode, ctypes.byref(out)),
            "lbimp_nn_search_ragged_workspace")
     return int(out.value)
@@ -335,7 +341,7 @@ def lbimp_autotune(ctx: Ctx, db: Db, queries: torch.Tensor, w: int, p: int, k: i
     if isinstance(mode, str):
         mode = MODES[mode]
     out = (_i32 * len(TUNE_KNOBS))()
-    _check(_lib.lbimp_autotune(ctx.sync_stream(), db.h, _dev(queries, "queries"), queries.shape[0], w, p, k, mode,
+    _check(_lib.lbimp_autotune(ctx.sync_stream(), db.h, _dev(queries, "queries"), queries.shape[0], w, _p(p), k, mode,
                                out), "lbimp_autotune")
     return {name: int(out[i]) for i, name in enumerate(TUNE_KNOBS)}
 

@@ -68,12 +68,12 @@ def _alone(L, ctx, handles, db_of, w, Ys, p, k, mode, n_of):
 
 
 @pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
-@pytest.mark.parametrize("p,k", [(1, 1), (2, 5)])
+@pytest.mark.parametrize("p,k", [(1, 1), (2, 5), (float("inf"), 3)])
 @pytest.mark.parametrize("graph,streams", [(0, 4), (1, 4), (0, 0), (1, 1)])
 def test_ragged_matches_oracle_and_alone(L, ctx, dbs, mode, p, k, graph, streams):
     _say(f"ragged mix mode={mode} p={p} k={k} graph={graph} streams={streams}")
     Xs, handles = dbs
-    db_of, w, Ys, offsets, packed = _mix(1 + p + 3 * k, 37, LENGTHS, BANDS)
+    db_of, w, Ys, offsets, packed = _mix(1 + min(p, 3) + 3 * k, 37, LENGTHS, BANDS)
     L.lbimp_ctx_set_option(ctx, "graph", graph)
     L.lbimp_ctx_set_option(ctx, "ragged_streams", streams)
     try:
