@@ -23,14 +23,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "1-NN DTW queries/sec (LB_Improved vs LB_Keogh vs brute); LB GB/s; p50/p99"
-# fp32 vector peak 157.3 TFLOP/s counts an FMA as 2 flops: 78.6e12 VALU lane-slots per second
-# (256 CUs x 128 lane-ops per clock x 2.4 GHz).  One LB_Keogh element is 2 comparisons (one
-# 3-operand med3, which issues in two slots), a subtract and an accumulate: 4 slots.  A DTW cell
-# is a subtract, a 3-way min (two slots) and an accumulate: 4 slots.
-VALU_PEAK_OPS = 157.3e12 / 2
+# fp32 vector peak 157.3 TFLOP/s counts an FMA as 2 flops: 78.65e12 VALU lane-instructions per
+# second (256 CUs x 4 SIMDs x 64 lanes / 2 cycles x 2.4 GHz).  Algorithmic instruction counts:
+# an LB_Keogh element is a clamp to the envelope (one med3), a subtract and an accumulate (add of
+# |d|, or fma for p = 2): 3 instructions; a DTW cell is a subtract, a 3-way min (min3) and an
+# accumulate: 3 instructions; an LB_Improved element about 9 (clamp, the running and block
+# max/min of the projection's envelope, the distance of y to it, the accumulate).  A model of
+# the issue cost, kept beside the count: a 3-operand med3/min3 issues in two slots, so an
+# LB_Keogh element or a DTW cell costs 4 slots.
+VALU_PEAK = 157.3e12 / 2
 HBM_PEAK_GBPS = 8000.0
-LBK_OPS_PER_ELEM = 4
-DTW_OPS_PER_CELL = 4
+LBK_INSTR_PER_ELEM = 3
+LBK_SLOTS_PER_ELEM_MODEL = 4
+DTW_INSTR_PER_CELL = 3
+LBI_INSTR_PER_ELEM = 9
 
 
 def sweep_traffic():
@@ -60,9 +66,23 @@ def log(msg):
 
 
 def time_mode(L, ctx, db, Yd, w, p, mode, steps, warmup):
+    """A step is one search over the batch plus the copy of its results (idx, dist) to pinned
+    host memory; each step ends when the results are on the host."""
     import torch
+    Q = Yd.shape[0]
+    idx = torch.empty((Q, 1), dtype=torch.int64, device="cuda")
+    dist = torch.empty((Q, 1), dtype=torch.float32, device="cuda")
+    idx_h = torch.empty((Q, 1), dtype=torch.int64, pin_memory=True)
+    dist_h = torch.empty((Q, 1), dtype=torch.float32, pin_memory=True)
+
+    def step():
+        L.lbimp_nn_search(ctx, db, Yd, w, p, 1, mode, idx=idx, dist=dist, stats=False)
+        idx_h.copy_(idx, non_blocking=True)
+        dist_h.copy_(dist, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+
     for _ in range(warmup):
-        L.lbimp_nn_search(ctx, db, Yd, w, p, 1, mode, stats=False)
+        step()
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -71,14 +91,49 @@ def time_mode(L, ctx, db, Yd, w, p, mode, steps, warmup):
     e0.record(s)
     for _ in range(steps):
         a = time.perf_counter()
-        L.lbimp_nn_search(ctx, db, Yd, w, p, 1, mode, stats=False)
-        torch.cuda.synchronize()
+        step()
         per.append((time.perf_counter() - a) * 1e3)
     e1.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
-    return dict(ms_per_step=ev_ms / steps, wall_ms_per_step=wall * 1e3 / steps, step_ms=per)
+    return dict(ms_per_step=ev_ms / steps, wall_ms_per_step=wall * 1e3 / steps, step_ms=per,
+                idx=idx_h.numpy()[:, 0].copy(), dist=dist_h.numpy()[:, 0].copy())
+
+
+def t_roof(mode, Q, N, n, w, st):
+    """Roofline time of one step from the measured counts: max(HBM bytes of the database read
+    once, 3 instructions per LB_Keogh element of every pair) + (9 per LB_Improved element of
+    every pass-1 survivor + 3 per DTW cell) / VALU peak.  DTW cells: every cell of the DTWs
+    that ran to the end, plus those that were abandoned counted at 0 cells (low) or in full
+    (high); the two bracket the cells actually computed."""
+    cells = n * (2 * w + 1) - w * (w + 1)
+    started, abandoned = float(st[:, 4].sum()), float(st[:, 5].sum())
+    if mode == "brute":
+        base = 0.0
+        lbi = 0.0
+    else:
+        base = max(N * n * 4 / (HBM_PEAK_GBPS * 1e9), LBK_INSTR_PER_ELEM * Q * N * n / VALU_PEAK)
+        survivors1 = float((st[:, 3] + st[:, 4] - st[:, 1]).sum())  # pass-1 survivors (seeds excluded)
+        lbi = LBI_INSTR_PER_ELEM * n * survivors1 / VALU_PEAK if mode == "improved" else 0.0
+    lo = base + lbi + DTW_INSTR_PER_CELL * cells * (started - abandoned) / VALU_PEAK
+    hi = base + lbi + DTW_INSTR_PER_CELL * cells * started / VALU_PEAK
+    return lo * 1e3, hi * 1e3
+
+
+def golden_errors(name, idx, dist, p):
+    """Index agreement and relative distance errors of the device's 1-NN against the oracle's
+    brute force, stored in tests/golden by tests/golden/make_full_size.py."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_nn.txt")
+    if not os.path.exists(path):
+        return None
+    rows = np.loadtxt(path, comments="#", dtype=np.float64, ndmin=2)
+    oi, od = rows[:, 1].astype(np.int64), rows[:, 2]
+    want = od if p == 1 else np.sqrt(od)
+    rel = np.abs(np.asarray(dist, np.float64) - want) / np.maximum(want, 1e-30)
+    return dict(queries=int(rows.shape[0]), index_agreement=float(np.mean(oi == np.asarray(idx))),
+                rel_err_max=float(rel.max()), rel_err_median=float(np.median(rel)),
+                rel_err_p99=float(np.percentile(rel, 99)))
 
 
 def stage_profile(L, ctx, db, Yd, w, p, mode, steps):
@@ -123,25 +178,62 @@ def single_query_lb_gbps(L, ctx, steps=20):
     return dict(db_bytes=nbytes, ms=ms, gbps=nbytes / ms / 1e6, frac_hbm=nbytes / ms / 1e6 / HBM_PEAK_GBPS)
 
 
-def cpu_baseline(X, Ys, w, p, gpu_idx, budget_s=12.0):
-    """The fp64 oracle (brute-force DTW over the whole database) on a bounded sample of queries."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(X, Ys, w, p, gpu_idx, budget_s=8.0):
+    """The fp64 oracle on the host: brute-force DTW over the whole database (the definition) on
+    all cores and on one core, and the paper's own sequential Algorithms 3 and 2 (one query per
+    thread, database order), each on a bounded sample of the headline's queries."""
     from oracle import native
     native.load()
     X64 = X.astype(np.float64)
-    t = time.perf_counter()
-    idx, _ = native.nn_bruteforce(X64, Ys[:1].astype(np.float64), w, p, 1)
-    first = time.perf_counter() - t
+    Y64 = Ys.astype(np.float64)
+    cores = len(os.sched_getaffinity(0))
+    native.set_num_threads(cores)
+    threads = native.num_threads()
+
+    def timed(fn, *a):
+        t = time.perf_counter()
+        r = fn(*a)
+        return r, time.perf_counter() - t
+
+    (idx, _), first = timed(native.nn_bruteforce, X64, Y64[:1], w, p, 1)
     more = int(max(0, min(Ys.shape[0] - 1, budget_s / max(first, 1e-3) - 1)))
-    t = time.perf_counter()
-    idx2, _ = native.nn_bruteforce(X64, Ys[1:1 + more].astype(np.float64), w, p, 1)
-    rest = time.perf_counter() - t
+    (idx2, _), rest = timed(native.nn_bruteforce, X64, Y64[1:1 + more], w, p, 1)
     nq = 1 + more
-    total = first + rest
     allidx = np.concatenate([idx[:, 0], idx2[:, 0]]) if more else idx[:, 0]
-    agree = float(np.mean(allidx == gpu_idx[:nq]))
-    return dict(value=nq / total, unit="queries/s", cores=native.num_threads(), kind="oracle",
-                sample=f"{nq} of {Ys.shape[0]} queries, brute-force fp64 DTW against all {X.shape[0]} candidates",
-                seconds=total, index_agreement=agree)
+    out = dict(value=nq / (first + rest), unit="queries/s", cores=threads, kind="oracle",
+               sample=f"{nq} of {Ys.shape[0]} queries, brute-force fp64 DTW against all {X.shape[0]} candidates, "
+                      f"{threads} threads", seconds=first + rest,
+               index_agreement_sample=float(np.mean(allidx == gpu_idx[:nq])), cpu_model=cpu_model(),
+               host_cores=cores)
+    native.set_num_threads(1)
+    _, t1 = timed(native.nn_bruteforce, X64, Y64[:1], w, p, 1)
+    out["brute_force_1_core"] = dict(value=1.0 / t1, unit="queries/s", sample="1 query")
+    # the paper's method on the host: one query per thread, sequential scan in database order
+    for name, improved in (("algorithm3_lb_improved", True), ("algorithm2_lb_keogh", False)):
+        r = {}
+        native.set_num_threads(1)
+        q1 = 4
+        (i1, _, c1), t = timed(native.nn_sequential, X64, Y64[:q1], w, p, improved)
+        r["1_core"] = dict(value=q1 / t, unit="queries/s", sample=f"{q1} queries")
+        native.set_num_threads(threads)
+        qa = min(Ys.shape[0], 2 * threads)
+        (ia, _, ca), t = timed(native.nn_sequential, X64, Y64[:qa], w, p, improved)
+        r["all_cores"] = dict(value=qa / t, unit="queries/s", sample=f"{qa} queries, {threads} threads")
+        r["same_index_as_device"] = float(np.mean(ia == gpu_idx[:qa]))
+        r["dtw_fraction"] = float(ca[:, 2].sum() / (qa * X.shape[0]))
+        out[name] = r
+    native.set_num_threads(threads)
+    return out
 
 
 def ragged_bench(L, steps, warmup):
@@ -206,7 +298,8 @@ def shape_bench(L, steps):
         r = {}
         for mode, k in (("improved", steps), ("keogh", steps), ("brute", 2)):
             t = time_mode(L, ctx, db, Yd, w, 1, mode, k, 1)
-            r[mode] = dict(qps=Q / (t["ms_per_step"] / 1e3), ms_per_step=t["ms_per_step"])
+            r[mode] = dict(qps=Q / (t["ms_per_step"] / 1e3), ms_per_step=t["ms_per_step"],
+                           oracle=golden_errors(f"shape512_w{w}", t["idx"], t["dist"], 1))
         _, _, st = L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, "improved")
         r["pruned_keogh"] = float(st[:, 2].sum() / (N * Q))
         r["pruned_improved"] = float(st[:, 3].sum() / (N * Q))
@@ -218,10 +311,49 @@ def shape_bench(L, steps):
     return out
 
 
-def serving_bench(L, rates, seconds, max_batch=512, slots=4, budget=16 << 30):
+def triangle_bench(L, ctx, count=100_000, n=100, steps=5):
+    """App. B: 100,000 triples (x, y, z) of 100-sample random walks (and white noise),
+    unconstrained DTW_1 and DTW_2 (w = n), C = DTW(x,z) / (DTW(x,y) + DTW(y,z)); one
+    lbimp_dtw_pairs call computes the 300,000 distances of a p."""
+    import torch
+    from paper_0811_3301_amd import gen
+    cells = n * n
+    out = dict(workload=f"{count} triples of {n}-sample series, unconstrained DTW (w = n)", pairs_per_call=3 * count,
+               paper_violation_share={"random_walk": {"p1": 0.20, "p2": 0.15}, "white_noise": {"p1": 0.0, "p2": 0.0}})
+    for kind in ("random_walk", "white_noise"):
+        X, Y, Z = (torch.from_numpy(a.astype(np.float32)).cuda() for a in gen.triangle_triples(count, n, kind))
+        A = torch.cat([X, Y, X]).contiguous()
+        B = torch.cat([Y, Z, Z]).contiguous()
+        dist = torch.empty(3 * count, dtype=torch.float32, device="cuda")
+        r = {}
+        for p in (1, 2):
+            L.lbimp_dtw_pairs(ctx, A, B, n, p, out=dist)
+            torch.cuda.synchronize()
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(steps):
+                L.lbimp_dtw_pairs(ctx, A, B, n, p, out=dist)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            d = dist.cpu().numpy().astype(np.float64).reshape(3, count)
+            C = d[2] / (d[0] + d[1])
+            r[f"p{p}"] = dict(violation_share=float(np.mean(C > 1)), C_max=float(C.max()), ms=ms,
+                              pairs_per_s=3 * count / ms * 1e3, cells_per_s=3 * count * cells / ms * 1e3,
+                              dtw_frac_of_alu_peak=DTW_INSTR_PER_CELL * 3 * count * cells / (ms / 1e3) / VALU_PEAK)
+        out[kind] = r
+        del X, Y, Z, A, B, dist
+    return out
+
+
+def serving_bench(L, rates, measured=20_000, warmup_s=2.0, max_batch=512, slots=4, budget=16 << 30):
     """Serving: Poisson arrivals over a resident 1,000,000 x 128 random-walk database (512 MB)
     and a 200,000 x 256 side database (20% of requests), w = round(0.1 n), k uniform over
-    {1, 5, 10}; continuous batching on `slots` in-flight batches under a device-memory budget."""
+    {1, 5, 10}; continuous batching on `slots` in-flight batches under a device-memory budget.
+    Each arrival rate runs one stream: warmup_s seconds of arrivals, then `measured` requests;
+    latencies (arrival to results on the host) and throughput come from the measured ones."""
+    from paper_0811_3301_amd.serve import latency_summary
     import torch
     from paper_0811_3301_amd import gen
     from paper_0811_3301_amd.serve import GpuExecutor, Request, serve
@@ -236,18 +368,26 @@ def serving_bench(L, rates, seconds, max_batch=512, slots=4, budget=16 << 30):
         _, sample = gen.make_serving_workload(rates[-1], 300, with_databases=False)
         ex.pretune([Request(rid=j, t_arrive=0.0, db=int(sample["db"][j]), y=sample["y"][j].astype(np.float32),
                             w=int(sample["w"][j]), k=int(sample["k"][j])) for j in range(300)])
-        for i, rate in enumerate([rates[-1]] + list(rates)):  # the first run warms the workspaces up
-            count = max(200, min(int(rate * seconds), 40_000))
+        for rate in rates:
+            warm = max(200, int(rate * warmup_s))
+            count = warm + measured
             _, req = gen.make_serving_workload(rate, count, with_databases=False)
             reqs = [Request(rid=j, t_arrive=float(req["t"][j]), db=int(req["db"][j]),
                             y=req["y"][j].astype(np.float32), w=int(req["w"][j]), k=int(req["k"][j]))
                     for j in range(count)]
-            _, summ = serve(reqs, ex, budget_bytes=budget, max_batch=max_batch)
-            if i > 0:
-                summ["offered_rate"] = rate
-                runs.append(summ)
-                log(f"serving at {rate} q/s: p50 {summ['p50_ms']:.3f} ms, p99 {summ['p99_ms']:.3f} ms, "
-                    f"{summ['qps']:.0f} q/s")
+            del req
+            results, whole = serve(reqs, ex, budget_bytes=budget, max_batch=max_batch)
+            meas = [r for r in results if r.rid >= warm]
+            summ = latency_summary(meas)
+            t0 = min(r.t_arrive for r in meas)
+            t1 = max(r.t_done for r in meas)
+            summ.update(offered_rate=rate, warmup_requests=warm, qps=len(meas) / max(t1 - t0, 1e-9),
+                        offered_qps=len(meas) / max(reqs[-1].t_arrive - reqs[warm].t_arrive, 1e-9),
+                        workspace_bytes=whole["workspace_bytes"])
+            runs.append(summ)
+            log(f"serving at {rate} q/s: p50 {summ['p50_ms']:.3f} ms, p99 {summ['p99_ms']:.3f} ms, "
+                f"{summ['qps']:.0f} q/s over {len(meas)} requests")
+            del reqs, results, meas
     finally:
         ex.close()
         for h in handles:
@@ -256,6 +396,7 @@ def serving_bench(L, rates, seconds, max_batch=512, slots=4, budget=16 << 30):
     return dict(workload="serving: Poisson arrivals, 80% n=128 over a resident 1,000,000-series database "
                          "(512 MB), 20% n=256 over a 200,000-series database, w=round(0.1 n), k in {1,5,10}, "
                          "two-pass search", slots=slots, max_batch=max_batch, memory_budget_bytes=budget,
+                protocol=f"{warmup_s:g} s of arrivals as warm-up, then {measured} measured requests per rate",
                 runs=runs)
 
 
@@ -269,9 +410,10 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the uneven-batch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-shapes", action="store_true", help="skip the shape-signature measurement")
+    ap.add_argument("--no-triangle", action="store_true", help="skip the App. B triangle-inequality workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
-    ap.add_argument("--only", choices=("ragged", "serving", "shapes"),
+    ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle"),
                     help="run only the uneven-batch or the serving measurement and print its JSON (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -298,8 +440,14 @@ def main():
     if args.only == "shapes":
         print(json.dumps(shape_bench(L, args.steps)), flush=True)
         return
+    if args.only in ("triangle", "lbsingle"):
+        ctx = L.Ctx(0)
+        out = triangle_bench(L, ctx) if args.only == "triangle" else single_query_lb_gbps(L, ctx, args.steps)
+        print(json.dumps(out), flush=True)
+        ctx.close()
+        return
     if args.only == "serving":
-        print(json.dumps(serving_bench(L, rates=(10_000,), seconds=0.3)), flush=True)
+        print(json.dumps(serving_bench(L, rates=(10_000,), measured=3000, warmup_s=0.3)), flush=True)
         return
     N, n, Q, w = 100_000, 256, 256, 26
     log("generating workload")
@@ -314,18 +462,25 @@ def main():
 
     log("timing two-pass p=1")
     imp = time_mode(L, ctx, db, Yd, w, 1, "improved", args.steps, args.warmup)
-    idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, "improved")
-    gpu_idx = idx.cpu().numpy()[:, 0]
+    gpu_idx = imp["idx"]
+    _, _, st = L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, "improved")
     stages = stage_profile(L, ctx, db, Yd, w, 1, "improved", max(3, args.steps // 2))
 
-    modes = {"improved": dict(qps=Q / (imp["ms_per_step"] / 1e3), ms_per_step=imp["ms_per_step"])}
+    def mode_entry(r, stats, mode):
+        lo, hi = t_roof(mode, Q, N, n, w, stats)
+        return dict(qps=Q / (r["ms_per_step"] / 1e3), ms_per_step=r["ms_per_step"],
+                    t_roof_ms=[lo, hi], roof_frac=[lo / r["ms_per_step"], hi / r["ms_per_step"]])
+
+    modes = {"improved": mode_entry(imp, st, "improved")}
+    accuracy = {"rw256_p1": golden_errors("rw256_p1", imp["idx"], imp["dist"], 1)}
     if not args.quick:
         for mode, steps in (("keogh", args.steps), ("brute", max(2, args.steps // 10))):
             log(f"timing {mode} p=1")
             r = time_mode(L, ctx, db, Yd, w, 1, mode, steps, 1)
-            modes[mode] = dict(qps=Q / (r["ms_per_step"] / 1e3), ms_per_step=r["ms_per_step"])
-            idx_m = L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, mode, stats=False)[0].cpu().numpy()[:, 0]
-            modes[mode]["same_result_as_two_pass"] = bool(np.array_equal(idx_m, gpu_idx))
+            _, _, st_m = L.lbimp_nn_search(ctx, db, Yd, w, 1, 1, mode)
+            modes[mode] = mode_entry(r, st_m, mode)
+            modes[mode]["same_result_as_two_pass"] = bool(np.array_equal(r["idx"], gpu_idx))
+            modes[mode]["oracle"] = golden_errors("rw256_p1", r["idx"], r["dist"], 1)
         log("timing two-pass p=2")
         r2 = time_mode(L, ctx, db, Yd, w, 2, "improved", args.steps, 1)
         rk2 = time_mode(L, ctx, db, Yd, w, 2, "keogh", args.steps, 1)
@@ -333,21 +488,25 @@ def main():
         p2 = dict(improved_qps=Q / (r2["ms_per_step"] / 1e3), keogh_qps=Q / (rk2["ms_per_step"] / 1e3),
                   pruned_keogh=float(st2[:, 2].sum() / (N * Q)), pruned_improved=float(st2[:, 3].sum() / (N * Q)),
                   dtw_fraction=float(st2[:, 4].sum() / (N * Q)))
+        accuracy["rw256_p2"] = golden_errors("rw256_p2", r2["idx"], r2["dist"], 2)
     else:
         p2 = None
 
     sweep_ms = stages["lb_keogh"]
     elems = Q * N * n
-    achieved = LBK_OPS_PER_ELEM * elems / (sweep_ms / 1e3) / 1e12
+    achieved = LBK_INSTR_PER_ELEM * elems / (sweep_ms / 1e3) / 1e12
     roofline = dict(bound="alu", kernel="k_lbk_sweep (LB_Keogh of every query x candidate)",
-                    achieved=achieved, peak=VALU_PEAK_OPS / 1e12, unit="TOP/s", frac=achieved * 1e12 / VALU_PEAK_OPS,
-                    traffic=sweep_traffic(), kernel_ms=sweep_ms, ops_per_element=LBK_OPS_PER_ELEM, elements=elems,
-                    algorithmic_hbm_bytes=N * n * 4 * (Q // 16) + Q * ((N + 63) // 64 * 64) * 4)
+                    achieved=achieved, peak=VALU_PEAK / 1e12, unit="T VALU lane-instructions/s",
+                    frac=achieved * 1e12 / VALU_PEAK, traffic=sweep_traffic(), kernel_ms=sweep_ms,
+                    instructions_per_element=LBK_INSTR_PER_ELEM, elements=elems,
+                    frac_issue_model=LBK_SLOTS_PER_ELEM_MODEL * elems / (sweep_ms / 1e3) / VALU_PEAK,
+                    issue_model="med3 issues in two slots: 4 slots per element",
+                    algorithmic_hbm_bytes=N * n * 4 + Q * ((N + 63) // 64 * 64) * 4)
     if "brute" in modes:
         cells = Q * N * (n * (2 * w + 1) - w * (w + 1))
         t = modes["brute"]["ms_per_step"] / 1e3
         modes["brute"]["dtw_cells_per_s"] = cells / t
-        modes["brute"]["dtw_frac_of_alu_peak"] = DTW_OPS_PER_CELL * cells / t / VALU_PEAK_OPS
+        modes["brute"]["dtw_frac_of_alu_peak"] = DTW_INSTR_PER_CELL * cells / t / VALU_PEAK
 
     lbg = None
     if not args.quick:
@@ -367,12 +526,20 @@ def main():
     serving = None
     if not (args.quick or args.no_serving):
         log("serving loop")
-        serving = serving_bench(L, rates=(1_000, 2_000, 5_000, 10_000, 20_000, 35_000, 50_000), seconds=0.5)
+        serving = serving_bench(L, rates=(1_000, 2_000, 5_000, 10_000, 20_000, 35_000, 50_000))
+
+    triangle = None
+    if not (args.quick or args.no_triangle):
+        log("App. B triangle-inequality workload (100000 triples, n=100, unconstrained DTW)")
+        triangle = triangle_bench(L, ctx)
 
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline")
         cpu = cpu_baseline(X, Ys, w, 1, gpu_idx)
+        if accuracy.get("rw256_p1"):
+            cpu["index_agreement"] = accuracy["rw256_p1"]["index_agreement"]
+            cpu["index_agreement_over"] = "all 256 queries against the oracle's brute force (tests/golden)"
 
     step_ms = np.array(imp["step_ms"])
     out = {
@@ -399,11 +566,13 @@ def main():
                            dtw_fraction=float(st[:, 4].sum() / (N * Q)),
                            abandoned_fraction_of_dtw=float(st[:, 5].sum() / max(1, st[:, 4].sum()))),
         "stage_ms_p1": stages,
+        "accuracy_vs_oracle": accuracy,
         "lb_single_query_hbm": lbg,
         "batch_latency_ms": dict(p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99))),
         "ragged": ragged,
         "shapes": shapes,
         "serving": serving,
+        "triangle": triangle,
     }
     print(json.dumps(out), flush=True)
     db.close()

@@ -147,6 +147,13 @@ int lbimp_lb_improved(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, cons
 int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, int32_t n, int32_t w, int32_t p,
                    float *dist);
 
+/* DTW_p(x_c, y_c) under |i-j| <= w (Sec. 4 recursion) for N pairs of rows: x and y device
+ * [N][n], dist device [N].  Each pair has its own query, as in the triples of the App. B
+ * triangle-inequality experiment; each pair is computed by one wave (bands wider than 63) or
+ * by a group of lanes of one wave (narrower bands, which leave the rest of the wave idle). */
+int lbimp_dtw_pairs(lbimp_ctx *ctx, const float *x, const float *y, int64_t N, int32_t n, int32_t w, int32_t p,
+                    float *dist);
+
 /* k nearest neighbours under DTW_p of each of Q queries (device [Q][n], n equal to the
  * database's length) in database `db` (Algorithms 2 and 3, generalised to DTW_p and k).
  * Outputs: idx device [Q][k] int64 and dist device [Q][k] float32, sorted by (distance,

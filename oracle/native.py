@@ -36,6 +36,7 @@ def load():
         build()
     lib = ctypes.CDLL(_LIB)
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     lib.orc_dtw_pow.restype = ctypes.c_double
     lib.orc_dtw_pow.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.orc_dtw_pow_many.argtypes = [_dp, ctypes.c_int64, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
@@ -63,6 +64,11 @@ def _p(p) -> int:
 
 def num_threads() -> int:
     return int(load().orc_num_threads())
+
+
+def set_num_threads(threads: int) -> None:
+    """Threads used by the OpenMP loops of the following calls."""
+    load().orc_set_num_threads(int(threads))
 
 
 def envelope(y, w):

@@ -43,6 +43,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the OpenMP loops below (the benchmark times the oracle on one core and on all). */
+void orc_set_num_threads(int threads) {
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+}
+
 /* Sec. 5: naive windowed max/min. */
 void orc_envelope(const double *y, int n, int w, double *U, double *L) {
     for (int i = 0; i < n; ++i) {

@@ -1,6 +1,6 @@
 """Build the HIP library liblbimp.so for gfx950 (in-tree, next to this file).
 
-    python -m paper_0811_3301_amd.build
+    python -m paper_0811_3301_amd.build [--incremental] [-v]
 
 Every source under csrc/ is compiled by hipcc with packed-FP32 instruction selection
 disabled, and linked into one shared library exporting the C-ABI of include/lbimp.h.
@@ -29,7 +29,26 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
+def _deps(src, seen=None):
+    """The file and every quoted #include it reaches in csrc/ or include/."""
+    seen = set() if seen is None else seen
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    for line in open(src):
+        line = line.strip()
+        if line.startswith("#include \""):
+            name = line.split('"')[1]
+            for d in (os.path.join(HERE, "csrc"), os.path.join(ROOT, "include")):
+                if os.path.exists(os.path.join(d, name)):
+                    _deps(os.path.join(d, name), seen)
+                    break
+    return seen
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those whose object is older than the source or
+    a header it includes) and link liblbimp.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
@@ -38,8 +57,12 @@ def build(verbose: bool = False) -> str:
     cmds = []
     for src in sources():
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
-        cmds.append([hipcc, *HIP_FLAGS, *inc, "-c", src, "-o", obj])
         objs.append(obj)
+        if incremental and os.path.exists(obj):
+            newest = max(os.path.getmtime(f) for f in _deps(src))
+            if newest <= os.path.getmtime(obj):
+                continue
+        cmds.append([hipcc, *HIP_FLAGS, *inc, "-c", src, "-o", obj])
 
     def run(cmd):
         if verbose:
@@ -64,4 +87,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

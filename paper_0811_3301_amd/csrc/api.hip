@@ -945,6 +945,38 @@ int lbimp_dtw_band(lbimp_ctx *ctx, const float *x, int64_t N, const float *y, in
     return LBIMP_OK;
 }
 
+int lbimp_dtw_pairs(lbimp_ctx *ctx, const float *x, const float *y, int64_t N, int32_t n, int32_t w, int32_t p,
+                    float *dist) {
+    if (int r = check_ctx(ctx)) return r;
+    if (int r = check_shape(N, n, w, p)) return r;
+    if (N == 0) return LBIMP_OK;
+    if (!x || !y || !dist) return fail(LBIMP_E_INVALID, "null pointer");
+    const int wb = band_of(n, w);
+    Carver cv{nullptr};
+    cv.take<long long>(2);
+    cv.take<int>(1);
+    cv.take<int>((size_t)N);
+    cv.take<u64>((size_t)N);
+    if (int r = reserve(ctx, cv.off)) return r;
+    Carver c2{static_cast<char *>(ctx->ws)};
+    long long *prefix = c2.take<long long>(2);
+    int *ctr = c2.take<int>(1);
+    int *self = c2.take<int>((size_t)N);
+    u64 *nothr = c2.take<u64>((size_t)N);
+    hipStream_t s = ctx->stream;
+    // pair c is query c (row c of y) against candidate c (row c of x): a list holding c for
+    // query c, one pair per query, computed by the group-of-lanes-per-pair kernels, which stage
+    // each pair's own query
+    HIPTRY(launch_fill_i32(ctr, 0, 1, s));
+    HIPTRY(launch_iota_i32(self, N, s));
+    HIPTRY(launch_fill_u64(nothr, kNoKey, N, s));
+    QueryData qd{y, n, nullptr, nullptr, 0};
+    PairList pl{self, 1, nullptr, 1};
+    HIPTRY(launch_dtw(p, x, n, wb, qd, pl, prefix, N, ctr, persistent_grid(ctx), nullptr, nothr, nullptr, 0, nullptr,
+                      nullptr, dist, false, true, nullptr, 0, nullptr, 0, s));
+    return LBIMP_OK;
+}
+
 int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                     int32_t k, int32_t mode, int64_t *idx, float *dist, lbimp_stats *stats) {
     if (int r = check_ctx(ctx)) return r;

@@ -65,6 +65,7 @@ hipError_t launch_items_prefix(const int *cnt, int64_t fixed, int64_t Q, int bat
 
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count, hipStream_t s);
 hipError_t launch_fill_i32(int *p, int v, int64_t count, hipStream_t s);
+hipError_t launch_iota_i32(int *p, int64_t count, hipStream_t s);  // p[i] = i
 
 // Pair list description for the persistent second-pass and DTW kernels.
 struct PairList {

@@ -567,6 +567,17 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
     return hipGetLastError();
 }
 
+__global__ void k_iota_i32(int *p, int64_t count) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < count) p[g] = (int)g;
+}
+
+hipError_t launch_iota_i32(int *p, int64_t count, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int *p, int v, int64_t count, hipStream_t s) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);

@@ -16,6 +16,7 @@ Workloads (each stands in for a data set of the paper's experiments, Sec. 10):
   bands, each length with its own database (uneven batches; not a paper experiment).
 * ``make_serving_workload``: a request stream over two resident databases (serving;
   not a paper experiment).
+* ``triangle_triples``: independent triples of random walks or white noise (App. B).
 
 Seeds follow ``SeedSequence([8113301, config_id, role, *extra])``, role 0 = database,
 1 = queries, 2 = arrivals and per-request draws.
@@ -145,6 +146,14 @@ def make_workload(name: str, N: int | None = None, Q: int | None = None):
         db = shape_signatures(N, n, rng(spec["config_id"], ROLE_DB))
         qs = shape_signatures(Q, n, rng(spec["config_id"], ROLE_QUERY))
     return db, qs
+
+
+def triangle_triples(count: int = 100_000, n: int = 100, kind: str = "random_walk", config_id: int = 6):
+    """``count`` triples (x, y, z) of independent series of length n (App. B experiment: random
+    walks or white noise, 100,000 triples of 100 samples).  Returns three [count][n] arrays."""
+    draw = random_walk if kind == "random_walk" else white_noise
+    role = 0 if kind == "random_walk" else 1
+    return tuple(draw(count, n, rng(config_id, role, j)) for j in range(3))
 
 
 RAGGED_LENGTHS = (64, 128, 256, 512, 1024)

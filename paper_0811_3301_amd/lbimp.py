@@ -52,6 +52,7 @@ SIGNATURES = {
     "lbimp_db_lb_keogh": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _vp]),
     "lbimp_lb_improved": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _i32, _i32, _vp]),
     "lbimp_dtw_band": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _i32, _i32, _vp]),
+    "lbimp_dtw_pairs": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _vp]),
     "lbimp_nn_search": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp,
                                        ctypes.POINTER(LbimpStats)]),
     "lbimp_nn_search_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp]),
@@ -239,6 +240,17 @@ def lbimp_dtw_band(ctx: Ctx, x: torch.Tensor, y: torch.Tensor, w: int, p: int, o
     out = _out(out, (N,), torch.float32, x)
     _check(_lib.lbimp_dtw_band(ctx.sync_stream(), _dev(x, "x"), N, _dev(y, "y"), n, w, _p(p), _dev(out, "dist")),
            "lbimp_dtw_band")
+    return out
+
+
+def lbimp_dtw_pairs(ctx: Ctx, x: torch.Tensor, y: torch.Tensor, w: int, p, out=None):
+    """DTW_p of row c of x against row c of y for every c (x, y: [N][n] float32 GPU tensors)."""
+    N, n = x.shape
+    if tuple(y.shape) != (N, n):
+        raise ValueError("x and y must have the same [N][n] shape")
+    out = _out(out, (N,), torch.float32, x)
+    _check(_lib.lbimp_dtw_pairs(ctx.sync_stream(), _dev(x, "x") if N else None, _dev(y, "y") if N else None, N, n, w,
+                                _p(p), _dev(out, "dist")), "lbimp_dtw_pairs")
     return out
 
 

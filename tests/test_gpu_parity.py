@@ -189,6 +189,21 @@ def test_paper_worked_examples_through_the_abi(L, ctx, golden_dir):
     assert done >= 40
 
 
+@pytest.mark.parametrize("N,n,w", [(70, 100, 99), (65, 64, 5), (40, 128, 13), (33, 300, 80), (20, 1000, 205),
+                                   (9, 2000, 1500), (5, 7, 100), (1, 1, 0)])
+@pytest.mark.parametrize("p", [1, 2, INF])
+def test_dtw_pairs(L, ctx, N, n, w, p):
+    """DTW of N independent pairs (row c of x against row c of y), each with its own query."""
+    _say(f"dtw_pairs N={N} n={n} w={w} p={p}")
+    X = walks(N, n, 30)
+    Y = walks(N, n, 31)
+    d = L.lbimp_dtw_pairs(ctx, to_dev(X), to_dev(Y), w, p).cpu().numpy()
+    wb = R.effective_band(n, w)
+    D = np.array([native.dtw_pow(X[c], Y[c], wb, p) for c in range(N)])
+    scale = np.array([lp_scale(X[c][None, :], Y[c], p)[0] for c in range(N)])
+    assert_close(d, rt(D, p), scale, "dtw_pairs")
+
+
 # ------------------------------------------------------------------ nearest-neighbour search
 def oracle_knn(X, Ys, w, p, k):
     idx, dist = native.nn_bruteforce(X, Ys, R.effective_band(X.shape[1], w), p, k)
