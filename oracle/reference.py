@@ -194,6 +194,52 @@ def lb_improved(x, y, U, L, w, p) -> float:
     return root(lb_improved_pow(x, y, U, L, w, p), p)
 
 
+# ---------------------------------------------------------------- piecewise sums P_d (Sec. 9)
+def pd_cover(n: int, d: int):
+    """The cover of Sec. 9: C_j = [j*m, (j+1)*m) for j < d-1 and C_{d-1} = [(d-1)*m, n), with
+    m = floor(n/d) (0-based, half-open).  When n < d the first d-1 parts are empty."""
+    m = n // d
+    return [(j * m, (j + 1) * m) for j in range(d - 1)] + [((d - 1) * m, n)]
+
+
+def piecewise_sums(x, cover) -> np.ndarray:
+    """P_d(x) = (sum_{i in C_j} x_i)_j (Sec. 9)."""
+    x = _as64(x)
+    return np.array([x[a:b].sum() for a, b in cover])
+
+
+def pd_bound_pow(x, U, L, p, d=8) -> float:
+    """Distance of P_d(x) to the box [P_d(L), P_d(U)] spanned by the envelope of the query
+    (Sec. 9), a lower bound of LB_Keogh: sum_j d(P_d(x)_j, [P_d(L)_j, P_d(U)_j]) for p = 1.
+
+    For p = 1 this is the bound the paper states.  For other p the term of part j is
+    d_j^p / |C_j|^(p-1) (and max_j d_j / |C_j| for p = inf): d_j <= sum_{i in C_j} d(x_i, [L_i, U_i])
+    (the sum of the clamped differences of one sign), and (sum over |C| terms)^p <= |C|^(p-1)
+    times the sum of their p-th powers (power-mean inequality); an empty part adds nothing."""
+    cover = pd_cover(len(_as64(x)), d)
+    px, pu, pl = piecewise_sums(x, cover), piecewise_sums(U, cover), piecewise_sums(L, cover)
+    dj = dist_to_interval(px, pl, pu)
+    size = np.array([b - a for a, b in cover], dtype=np.float64)
+    live = size > 0
+    if p == INF:
+        return float(np.max(dj[live] / size[live])) if live.any() else 0.0
+    return float(np.sum(dj[live] ** p / size[live] ** (p - 1)))
+
+
+def pd_bound_pow_many(X, U, L, p, d=8) -> np.ndarray:
+    """pd_bound_pow of every row of X (the same formula, one row per vector lane)."""
+    X = _as64(X)
+    cover = pd_cover(X.shape[1], d)
+    px = np.stack([X[:, a:b].sum(axis=1) for a, b in cover], axis=1)
+    pu, pl = piecewise_sums(U, cover), piecewise_sums(L, cover)
+    dj = np.where(px > pu, px - pu, np.where(px < pl, pl - px, 0.0))
+    size = np.array([b - a for a, b in cover], dtype=np.float64)
+    live = size > 0
+    if p == INF:
+        return (dj[:, live] / size[live]).max(axis=1) if live.any() else np.zeros(X.shape[0])
+    return (dj[:, live] ** p / size[live] ** (p - 1)).sum(axis=1)
+
+
 # ---------------------------------------------------------------- DTW_p (Sec. 4)
 def dtw_pow(x, y, w, p) -> float:
     """DTW_p(x,y)^p by dynamic programming over the band |i-j| <= w (Sec. 4 recursion).

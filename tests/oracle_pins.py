@@ -234,3 +234,33 @@ def check_lemma1(seed=8):
         b = g.uniform(a, c)
         for p in (1, 2, 3, 4):
             assert (c - a) ** p >= ((c - b) ** p + (b - a) ** p) * (1 - 1e-12)
+
+
+def check_pd_bound(pd_bound_pow, pd_cover, seed=21):
+    """P_d (Sec. 9): the cover is d disjoint parts of width floor(n/d), the last taking the rest;
+    d(P_d(x), [P_d(L), P_d(U)]) <= LB_Keogh <= DTW (Sec. 9 chain, extended to p = 2 and inf);
+    d = n reduces to LB_Keogh exactly (one element per part); candidates entirely above the
+    envelope reduce it to LB_Keogh_1 exactly for p = 1 (every clamped difference has one sign)."""
+    g = np.random.default_rng(seed)
+    for n in (1, 2, 5, 7, 8, 9, 16, 100, 131):
+        for d in (1, 3, 8, n):
+            cover = pd_cover(n, d)
+            m = n // d
+            assert len(cover) == d and cover[-1][1] == n
+            assert all(b - a == m for a, b in cover[:-1]) and cover[-1][1] - cover[-1][0] == n - (d - 1) * m
+            assert all(cover[j][1] == cover[j + 1][0] for j in range(d - 1)) and cover[0][0] == 0
+    for t in range(120):
+        n = int(g.integers(1, 60))
+        w = int(g.integers(0, n + 1))
+        d = int(g.integers(1, 12))
+        x = np.cumsum(g.standard_normal(n))
+        y = np.cumsum(g.standard_normal(n))
+        U, L = R.envelope_naive(y, w)
+        for p in PS:
+            b = pd_bound_pow(x, U, L, p, d)
+            k = R.lb_keogh_pow(x, U, L, p)
+            assert -1e-12 <= b <= k * (1 + 1e-12) + 1e-12, (n, w, d, p, b, k)
+            assert k <= R.dtw_pow(x, y, w, p) * (1 + 1e-12) + 1e-12
+            assert _rel_close(pd_bound_pow(x, U, L, p, n), k, 1e-12), (n, w, p)
+        above = U + np.abs(g.standard_normal(n)) + 0.1
+        assert _rel_close(pd_bound_pow(above, U, L, 1, d), R.lb_keogh_pow(above, U, L, 1), 1e-12)

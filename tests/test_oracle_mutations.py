@@ -136,3 +136,37 @@ def _lbi_inf_sum(x, y, U, L, w, p):
 def test_lb_mistakes_are_caught(lbk, lbi):
     with pytest.raises(AssertionError):
         P.check_lb_chain(lbk, lbi, R.dtw_pow)
+
+
+def _pd_unscaled(x, U, L, p, d=8):
+    # mistake: the p-th powers of the part distances summed without the 1/|C|^(p-1) factor
+    cover = R.pd_cover(len(x), d)
+    px, pu, pl = (R.piecewise_sums(v, cover) for v in (x, U, L))
+    dj = R.dist_to_interval(px, pl, pu)
+    return float(np.max(dj)) if p == R.INF else float(np.sum(dj ** p))
+
+
+def _pd_swapped(x, U, L, p, d=8):
+    # mistake: the box taken from the upper envelope at its lower side
+    return R.pd_bound_pow(x, L, U, p, d)
+
+
+def _cover_ceil(n, d):
+    # mistake: parts of width ceil(n/d), which overrun the series for the last parts
+    m = -(-n // d)
+    return [(j * m, min(n, (j + 1) * m)) for j in range(d - 1)] + [(min(n, (d - 1) * m), n)]
+
+
+def _pd_with_ceil_cover(x, U, L, p, d=8):
+    cover = _cover_ceil(len(x), d)
+    px, pu, pl = (R.piecewise_sums(v, cover) for v in (x, U, L))
+    dj = R.dist_to_interval(px, pl, pu)
+    size = np.array([max(b - a, 1) for a, b in cover], dtype=float)
+    return float(np.max(dj / size)) if p == R.INF else float(np.sum(dj ** p / size ** (p - 1)))
+
+
+@pytest.mark.parametrize("fn,cover", [(_pd_unscaled, R.pd_cover), (_pd_swapped, R.pd_cover),
+                                      (_pd_with_ceil_cover, _cover_ceil)])
+def test_pd_mistakes_are_caught(fn, cover):
+    with pytest.raises(AssertionError):
+        P.check_pd_bound(fn, cover)

@@ -161,3 +161,18 @@ def test_c_dtw_matches_python_large():
             a = native.dtw_pow_many(X, y, w, p)
             b = R.dtw_pow_many(X, y, R.effective_band(n, w), p)
             assert np.allclose(a, b, rtol=1e-12, atol=0)
+
+
+def test_pd_bound():
+    P.check_pd_bound(R.pd_bound_pow, R.pd_cover)
+
+
+def test_pd_bound_many_matches_rows():
+    g = np.random.default_rng(22)
+    for n, w, d in ((50, 5, 8), (7, 3, 8), (131, 13, 8), (64, 0, 4)):
+        X = np.cumsum(g.standard_normal((30, n)), axis=1)
+        U, L = R.envelope_naive(np.cumsum(g.standard_normal(n)), w)
+        for p in (1, 2, math.inf):
+            many = R.pd_bound_pow_many(X, U, L, p, d)
+            for c in range(X.shape[0]):
+                assert P._rel_close(many[c], R.pd_bound_pow(X[c], U, L, p, d), 1e-12)
