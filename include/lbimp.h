@@ -54,11 +54,13 @@ enum {
     LBIMP_MODE_IMPROVED = 2  /* Algorithm 3: LB_Keogh, then LB_Improved, then DTW */
 };
 
-/* Per-query counters of one search.  candidates = seeded + pruned_keogh +
+/* Per-query counters of one search.  candidates = seeded + pruned_pd + pruned_keogh +
  * pruned_improved + (dtw_started - seeded).  Seeds are the candidates with the
- * smallest LB_Keogh whose DTW sets the initial threshold; every later candidate is
- * pruned against that threshold, so the counts do not depend on thread timing.
- * dtw_abandoned counts DTWs stopped early once they could no longer win; it may
+ * smallest first bound (LB_Keogh, or the piecewise-sum bound with the "pd_prefilter"
+ * option) whose DTW sets the initial threshold; every later candidate is pruned against
+ * that threshold, so the counts do not depend on thread timing.  pruned_pd counts the
+ * candidates the piecewise-sum bound of Sec. 9 removed before LB_Keogh (0 without the
+ * option).  dtw_abandoned counts DTWs stopped early once they could no longer win; it may
  * vary between runs because the best-so-far tightens concurrently. */
 typedef struct {
     int64_t candidates;
@@ -67,6 +69,7 @@ typedef struct {
     int64_t pruned_improved;
     int64_t dtw_started;
     int64_t dtw_abandoned;
+    int64_t pruned_pd;
 } lbimp_stats;
 
 typedef struct lbimp_ctx lbimp_ctx;
@@ -99,7 +102,12 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *   "ragged_streams" 0..4 (default 4): streams over which lbimp_nn_search_ragged spreads its
  *                   groups; 0 or 1 runs them one after another on the context's stream (with
  *                   "graph" 0 no other stream is touched, which suits callers that already
- *                   overlap several contexts).
+ *                   overlap several contexts);
+ *   "pd_prefilter"  0/1 (default 0): the searches start with pass 0, the piecewise-sum bound of
+ *                   Sec. 9 (d = 8 part sums per series, 64 bytes per candidate), seed the
+ *                   threshold from its smallest values, and compute LB_Keogh only of the
+ *                   candidates it keeps, reading their rows; it pays where the first pass is
+ *                   bound by database reads (a few queries per database sweep).
  * Returns LBIMP_E_INVALID for an unknown name or an out-of-range value. */
 int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
 
@@ -107,14 +115,17 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
  * With timing on, lbimp_ctx_stage_times waits for the last search and writes up to
  * `max` stage durations in milliseconds to host array `ms` (order: envelope, lb_keogh
  * sweep, seed selection, seed DTW, compaction, lb_improved, dtw, finalize); it returns
- * the number of stages written, or a negative status. */
+ * the number of stages written, or a negative status.  With "pd_prefilter" the second
+ * stage is the pass-0 scan and the compaction stage holds the pass-0 compaction and the
+ * LB_Keogh of its survivors. */
 int lbimp_ctx_set_timing(lbimp_ctx *ctx, int enable);
 int lbimp_ctx_stage_times(lbimp_ctx *ctx, float *ms, int max);
 
 /* Device-resident database (the flat file of the paper's Sec. 10, kept in HBM).
  * `rows` is a device [N][n] float32 array; it is copied (row-major and in the
- * 64-candidate interleaved layout of the LB_Keogh sweep), so the caller may free it
- * after the call returns and the stream has run.  N may be 0. */
+ * 64-candidate interleaved layout of the LB_Keogh sweep) and summarised by its fp64 sums
+ * over the 8 parts of the Sec. 9 cover, so the caller may free it after the call returns
+ * and the stream has run.  N may be 0. */
 int lbimp_db_create(lbimp_ctx *ctx, const float *rows, int64_t N, int32_t n, lbimp_db **out);
 void lbimp_db_destroy(lbimp_db *db);
 int64_t lbimp_db_size(const lbimp_db *db);
@@ -135,6 +146,15 @@ int lbimp_lb_keogh(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, const f
  * U, L device [Q][n]; lb device [Q][N] (row q holds LB_Keogh_p of every candidate). */
 int lbimp_db_lb_keogh(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const float *L, int64_t Q,
                       int32_t p, float *lb);
+
+/* Piecewise-sum lower bound of Sec. 9 over a resident database for Q query envelopes: with
+ * the cover C_j = [j m, (j+1) m), j < 7, and C_7 = [7 m, n), m = floor(n/8), and P(v) the part
+ * sums of v, lb[q][c] = sum_j d(P(x_c)_j, [P(L)_j, P(U)_j]) for p = 1 (the paper's bound of
+ * LB_Keogh_1); for p = 2 the root of sum_j d_j^2 / |C_j|, for p = infinity max_j d_j / |C_j|
+ * (power-mean inequality; both stay below LB_Keogh_p).  Sums in fp64, the bound rounded down
+ * to float32.  U, L device [Q][n]; lb device [Q][N]. */
+int lbimp_db_pd_bound(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const float *L, int64_t Q, int32_t p,
+                      float *lb);
 
 /* LB_Improved_p(x_c, y) (Sec. 8): LB_Keogh_p(x_c,y)^p + LB_Keogh_p(y, H(x_c,y))^p, the
  * second term against the envelope (same w) of the projection x' = H(x_c, y).
@@ -209,8 +229,8 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
  * "autotune" set, those calls tune a shape they meet for the first time by themselves.
  * choice: host [LBIMP_TUNE_KNOBS] or NULL, receives {seeds, sweep_shape, lbi_pipeline,
  * survivors' DTW group-per-pair, seeding DTW lane-per-pair, abandon bound with the LB_Keogh
- * tail}.  Waits for the stream. */
-#define LBIMP_TUNE_KNOBS 6
+ * tail, pass 0 with the piecewise-sum bound}.  Waits for the stream. */
+#define LBIMP_TUNE_KNOBS 7
 int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                    int32_t k, int32_t mode, int32_t *choice);
 

@@ -112,6 +112,7 @@ struct lbimp_ctx {
     int sweep_shape = 0;           // option "sweep_shape"
     bool use_graph = true;         // option "graph" (lbimp_nn_search_ragged)
     int ragged_streams = kPoolStreams;  // option "ragged_streams"
+    bool pd_prefilter = false;          // option "pd_prefilter"
     // ragged batches: stream pool, captured graph, pinned staging of the grouping metadata
     hipStream_t graph_stream = nullptr;
     hipStream_t pool[kPoolStreams] = {};
@@ -132,6 +133,7 @@ struct lbimp_db {
     int n = 0;
     float *rows = nullptr;  // [N][n] row-major copy (gathers of the second pass and the DTW)
     float4 *il = nullptr;   // interleaved tiles for the LB_Keogh sweep
+    double *pd = nullptr;   // [N][kPdParts] piecewise sums (Sec. 9) of the pass-0 scan
 };
 
 static int persistent_grid(const lbimp_ctx *ctx) { return std::max(1, ctx->num_cu); }  // CUs; kernels size by occupancy
@@ -203,6 +205,7 @@ struct Knobs {
     bool dtw_group;     // survivors' DTW with a group of lanes per pair (else a lane per pair)
     bool seed_lane;     // seeding DTWs with a lane per pair (else a group of lanes per pair)
     bool cascade;       // abandon on the row minimum plus the LB_Keogh terms still to come
+    bool pd = false;    // pass 0: piecewise-sum bound of every candidate, LB_Keogh only of its survivors
 };
 
 struct SearchSpec {  // Q queries of one length against one database
@@ -222,14 +225,15 @@ struct SearchDims {
     int n, n4, ldq, wb, qg, S, WL, k, p;
     int64_t N, Np, Q, Qp, ldres, nw;
     size_t ring_bytes;  // strip-boundary scratch of the wide-band DTW
-    bool brute, improved, from_minima;
+    bool brute, improved, from_minima, pd;
 };
 
 struct SearchBufs {
     float *Ue, *Le, *S1, *ring;
-    int *seeds, *list1, *list2, *counters;
+    int *seeds, *list0, *list1, *list2, *counters;
     u64 *best, *thr, *res, *wmin;
     long long *prefix;
+    double *qpd;
 };
 
 int dims_of(const SearchSpec &sp, int num_cu, SearchDims &d) {
@@ -251,7 +255,8 @@ int dims_of(const SearchSpec &sp, int num_cu, SearchDims &d) {
     if (d.improved && d.WL == 0)
         return fail(LBIMP_E_UNSUPPORTED, "LB_Improved state for n = %d, w = %d exceeds LDS", d.n, d.wb);
     d.ldres = d.brute ? std::max<int64_t>(d.N, 1) : d.S + d.N;
-    d.nw = sweep_waves(sp.kn.sweep_shape, d.N, sp.Q);
+    d.pd = sp.kn.pd && !d.brute;
+    d.nw = d.pd ? pd_scan_waves(d.N) : sweep_waves(sp.kn.sweep_shape, d.N, sp.Q);
     // seeds come from the per-wave minima of the sweep once there are enough of them
     d.from_minima = !d.brute && d.nw >= 4 * (int64_t)kMaxSeeds;
     d.ring_bytes = dtw_strip_scratch(d.p, d.n, d.wb, num_cu);
@@ -267,9 +272,11 @@ void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
     b.best = c.take<u64>((size_t)d.Q);
     b.thr = c.take<u64>((size_t)d.Q);
     b.res = (d.k > 1 || !any) ? c.take<u64>((size_t)d.Q * d.ldres) : nullptr;
+    b.list0 = (d.pd && any) ? c.take<int>((size_t)d.Q * d.N) : nullptr;
+    b.qpd = (d.pd && any) ? c.take<double>((size_t)d.Q * 2 * kPdParts) : nullptr;
     b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.N);
     b.list2 = (d.improved && any) ? c.take<int>((size_t)d.Q * d.N) : nullptr;
-    b.counters = c.take<int>((size_t)d.Q * 4);  // cnt1, cnt2, rescnt, abandoned ([4][Q])
+    b.counters = c.take<int>((size_t)d.Q * kCounters);  // cnt1, cnt2, rescnt, abandoned, cnt0 ([kCounters][Q])
     b.prefix = c.take<long long>((size_t)d.Q + 1);
     b.wmin = (d.from_minima && any) ? c.take<u64>((size_t)d.Q * d.nw) : nullptr;
     b.ring = (d.ring_bytes && any) ? c.take<float>(d.ring_bytes / sizeof(float)) : nullptr;
@@ -282,13 +289,15 @@ void fill_stats(const SearchDims &d, int64_t Q, const int *h, const int64_t *ids
         st.seeded = d.N ? d.S : 0;
         st.dtw_abandoned = d.brute ? 0 : h[3 * Q + q];
         if (d.N == 0) {
-            st = lbimp_stats{0, 0, 0, 0, 0, 0};
+            st = lbimp_stats{0, 0, 0, 0, 0, 0, 0};
         } else if (d.brute) {
-            st.pruned_keogh = st.pruned_improved = 0;
+            st.pruned_pd = st.pruned_keogh = st.pruned_improved = 0;
             st.dtw_started = d.N;
         } else {
             const int64_t c1 = h[q], c2 = d.improved ? h[Q + q] : c1;
-            st.pruned_keogh = d.N - d.S - c1;
+            const int64_t c0 = d.pd ? h[4 * Q + q] : d.N - d.S;  // pass-0 survivors
+            st.pruned_pd = d.N - d.S - c0;
+            st.pruned_keogh = c0 - c1;
             st.pruned_improved = c1 - c2;
             st.dtw_started = d.S + c2;
         }
@@ -306,9 +315,10 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     const int64_t Q = d.Q, N = d.N;
     const int n = d.n, wb = d.wb, p = d.p, k = d.k;
     const int ldo = sp.ldo ? sp.ldo : k;
-    int *cnt1 = b.counters, *cnt2 = b.counters + Q, *rescnt = b.counters + 2 * Q, *abandoned = b.counters + 3 * Q;
+    int *cnt1 = b.counters, *cnt2 = b.counters + Q, *rescnt = b.counters + 2 * Q, *abandoned = b.counters + 3 * Q,
+        *cnt0 = b.counters + 4 * Q;
     if (N == 0) {  // nothing to search: every slot is empty
-        HIPTRY(launch_fill_i32(b.counters, 0, Q * 4, s));
+        HIPTRY(launch_fill_i32(b.counters, 0, Q * kCounters, s));
         for (int i = 0; i <= 7; ++i) stage(i);
         HIPTRY(launch_finalize_k(b.res, 1, rescnt, Q, k, sp.kq, ldo, p, sp.idx, sp.dist, sp.qmap, s));
         stage(8);
@@ -331,9 +341,15 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
                           k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, nullptr, nullptr, false, false, b.ring,
                           d.ring_bytes, nullptr, 0, s));
     } else {
-        // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
-        HIPTRY(launch_lbk_sweep(p, sp.kn.sweep_shape, db->il, N, d.n4, reinterpret_cast<float4 *>(b.Ue),
-                                reinterpret_cast<float4 *>(b.Le), d.n4, Q, b.S1, d.Np, true, false, b.wmin, s));
+        if (d.pd) {
+            // pass 0: the piecewise-sum bound (Sec. 9) of every candidate, 64 bytes per candidate
+            HIPTRY(launch_pd_query(b.Ue, b.Le, d.ldq, Q, n, b.qpd, s));
+            HIPTRY(launch_pd_scan(p, db->pd, N, n, b.qpd, Q, b.S1, d.Np, true, false, b.wmin, s));
+        } else {
+            // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
+            HIPTRY(launch_lbk_sweep(p, sp.kn.sweep_shape, db->il, N, d.n4, reinterpret_cast<float4 *>(b.Ue),
+                                    reinterpret_cast<float4 *>(b.Le), d.n4, Q, b.S1, d.Np, true, false, b.wmin, s));
+        }
         stage(2);
         HIPTRY(launch_select_seeds(b.S1, d.Np, N, Q, d.S, b.wmin, d.nw, b.seeds, s));
         stage(3);
@@ -346,7 +362,15 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
                           d.ring_bytes, nullptr, 0, s));
         if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, sp.kq, b.thr, s));
         stage(4);
-        HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
+        if (d.pd) {
+            // the pass-0 survivors, then LB_Keogh of their rows (pass 1), which keeps its own survivors
+            HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list0, N, cnt0, s));
+            HIPTRY(launch_items_prefix(cnt0, 0, Q, lbk_gather_batch(), b.prefix, s));
+            HIPTRY(launch_lbk_gather(p, db->rows, n, qd, PairList{b.list0, N, cnt0, 0}, b.prefix, Q, grid, b.S1, d.Np,
+                                     T, b.list1, N, cnt1, s));
+        } else {
+            HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
+        }
         stage(5);
         PairList dl{b.list1, N, cnt1, 0};
         if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
@@ -372,7 +396,7 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
 }
 
 static Knobs ctx_knobs(const lbimp_ctx *ctx) {
-    return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false, true};
+    return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false, true, ctx->pd_prefilter};
 }
 
 static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int mode) {
@@ -380,12 +404,12 @@ static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int
 }
 
 static Knobs knobs_of(const std::array<int, kTuneKnobs> &v) {
-    return Knobs{v[0], v[2] != 0, v[1], v[3] != 0, v[4] != 0, v[5] != 0};
+    return Knobs{v[0], v[2] != 0, v[1], v[3] != 0, v[4] != 0, v[5] != 0, v[6] != 0};
 }
 
 static std::array<int, kTuneKnobs> knob_values(const Knobs &k) {
     return {k.seeds, k.sweep_shape, k.lbi_pipeline ? 1 : 0, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0,
-            k.cascade ? 1 : 0};
+            k.cascade ? 1 : 0, k.pd ? 1 : 0};
 }
 
 // The tuned choice for this batch shape if there is one, else the context's options.
@@ -412,16 +436,17 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     // workspace: [queries (gathered) | offsets | idx | dist][search buffers of the largest candidate]
     size_t search_bytes = 0;
     for (int sd : seed_opts)
-        for (int sh : shape_opts) {
-            SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr,
-                          Knobs{sd, true, sh, false, false, true}};
-            SearchDims d;
-            if (int r = dims_of(sp, ctx->num_cu, d)) return r;
-            SearchBufs b;
-            Carver cv{nullptr};
-            layout(cv, d, b);
-            search_bytes = std::max(search_bytes, cv.off);
-        }
+        for (int sh : shape_opts)
+            for (bool pdv : {false, true}) {
+                SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr,
+                              Knobs{sd, true, sh, false, false, true, pdv}};
+                SearchDims d;
+                if (int r = dims_of(sp, ctx->num_cu, d)) return r;
+                SearchBufs b;
+                Carver cv{nullptr};
+                layout(cv, d, b);
+                search_bytes = std::max(search_bytes, cv.off);
+            }
     auto carve_tune = [&](Carver &c, float *&qb, int64_t *&ob, int64_t *&ib, float *&db_) {
         qb = qdev ? nullptr : c.take<float>((size_t)Q * n);
         ob = qdev ? nullptr : c.take<int64_t>((size_t)Q);
@@ -520,6 +545,9 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     if (!brute) {
         Knobs kn = best;
         kn.cascade = !kn.cascade;
+        if (int r = consider(kn)) return r;
+        kn = best;
+        kn.pd = !kn.pd;  // pass 0 pays where the first pass is bound by database reads (few queries)
         if (int r = consider(kn)) return r;
     }
     ctx->tuned[tune_key(db, Q, wb, p, k, mode)] = knob_values(best);
@@ -751,6 +779,8 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         if (value < 0 || value > kPoolStreams)
             return fail(LBIMP_E_INVALID, "ragged_streams must be in [0, %d]", kPoolStreams);
         ctx->ragged_streams = (int)value;
+    } else if (!strcmp(name, "pd_prefilter")) {
+        ctx->pd_prefilter = value != 0;
     } else if (!strcmp(name, "sweep_shape")) {
         if (value < 0 || value > 5) return fail(LBIMP_E_INVALID, "sweep_shape must be in [0, 5]");
         ctx->sweep_shape = (int)value;
@@ -789,7 +819,9 @@ int lbimp_db_create(lbimp_ctx *ctx, const float *rows, int64_t N, int32_t n, lbi
     const int64_t T = (N + 63) / 64;
     size_t rbytes = sizeof(float) * (size_t)std::max<int64_t>(N, 1) * n;
     size_t ibytes = sizeof(float4) * (size_t)std::max<int64_t>(T, 1) * n4 * 64;
-    if (hipMalloc(&db->rows, rbytes) != hipSuccess || hipMalloc(&db->il, ibytes) != hipSuccess) {
+    size_t pbytes = sizeof(double) * (size_t)std::max<int64_t>(N, 1) * kPdParts;
+    if (hipMalloc(&db->rows, rbytes) != hipSuccess || hipMalloc(&db->il, ibytes) != hipSuccess ||
+        hipMalloc(&db->pd, pbytes) != hipSuccess) {
         (void)hipGetLastError();
         lbimp_db_destroy(db);
         return fail(LBIMP_E_NOMEM, "database allocation failed");
@@ -798,6 +830,7 @@ int lbimp_db_create(lbimp_ctx *ctx, const float *rows, int64_t N, int32_t n, lbi
         hipError_t e = hipMemcpyAsync(db->rows, rows, sizeof(float) * (size_t)N * n, hipMemcpyDeviceToDevice,
                                       ctx->stream);
         if (e == hipSuccess) e = launch_pack(rows, N, n, db->il, ctx->stream);
+        if (e == hipSuccess) e = launch_pd_rows(rows, N, n, db->pd, ctx->stream);
         if (e != hipSuccess) {
             lbimp_db_destroy(db);
             return fail(LBIMP_E_DEVICE, "database upload: %s", hipGetErrorString(e));
@@ -813,6 +846,7 @@ void lbimp_db_destroy(lbimp_db *db) {
     (void)hipDeviceSynchronize();
     if (db->rows) (void)hipFree(db->rows);
     if (db->il) (void)hipFree(db->il);
+    if (db->pd) (void)hipFree(db->pd);
     delete db;
 }
 
@@ -872,6 +906,23 @@ int lbimp_db_lb_keogh(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const 
     HIPTRY(launch_pad_env(U, L, Q, Qp, n, Ud, Ld, n4 * 4, ctx->stream));
     HIPTRY(launch_lbk_sweep(p, ctx->sweep_shape, db->il, db->N, n4, reinterpret_cast<float4 *>(Ud), reinterpret_cast<float4 *>(Ld), n4,
                             Q, lb, db->N, false, true, nullptr, ctx->stream));
+    return LBIMP_OK;
+}
+
+int lbimp_db_pd_bound(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const float *L, int64_t Q, int32_t p,
+                      float *lb) {
+    if (int r = check_ctx(ctx)) return r;
+    if (!db) return fail(LBIMP_E_INVALID, "null database");
+    if (int r = check_shape(Q, db->n, 0, p)) return r;
+    if (Q == 0 || db->N == 0) return LBIMP_OK;
+    if (!U || !L || !lb) return fail(LBIMP_E_INVALID, "null pointer");
+    Carver cv{nullptr};
+    cv.take<double>((size_t)Q * 2 * kPdParts);
+    if (int r = reserve(ctx, cv.off)) return r;
+    Carver c2{static_cast<char *>(ctx->ws)};
+    double *qpd = c2.take<double>((size_t)Q * 2 * kPdParts);
+    HIPTRY(launch_pd_query(U, L, db->n, Q, db->n, qpd, ctx->stream));
+    HIPTRY(launch_pd_scan(p, db->pd, db->N, db->n, qpd, Q, lb, db->N, false, true, nullptr, ctx->stream));
     return LBIMP_OK;
 }
 
@@ -1005,7 +1056,7 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     if (int r = enqueue_search(ctx, sp, d, bufs, ctx->stream, true)) return r;
     ctx->timed_valid = ctx->timing;
     if (stats) {
-        std::vector<int> h((size_t)Q * 4);
+        std::vector<int> h((size_t)Q * kCounters);
         HIPTRY(hipMemcpyAsync(h.data(), bufs.counters, sizeof(int) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
         HIPTRY(hipStreamSynchronize(ctx->stream));
         fill_stats(d, Q, h.data(), nullptr, stats);
@@ -1151,7 +1202,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         mix((uint64_t)(specs[g].k * 2 + (plan.mixed_k[g] ? 1 : 0)));
         const Knobs &kn = specs[g].kn;
         mix((uint64_t)(kn.seeds * 1000000 + kn.sweep_shape * 10000 + kn.lbi_pipeline * 1000 + kn.dtw_group * 100 +
-                       kn.seed_lane * 10 + kn.cascade));
+                       kn.seed_lane * 10 + kn.cascade + (kn.pd ? 100000000 : 0)));
     }
     if (!ctx->use_graph && width <= 1) {
         if (int r = enqueue_all(ctx->stream)) return r;
@@ -1189,7 +1240,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     if (stats) {
         HIPTRY(hipStreamSynchronize(ctx->stream));
         for (int g = 0; g < G; ++g) {
-            std::vector<int> h((size_t)specs[g].Q * 4);
+            std::vector<int> h((size_t)specs[g].Q * kCounters);
             HIPTRY(hipMemcpy(h.data(), bufs[g].counters, sizeof(int) * h.size(), hipMemcpyDeviceToHost));
             const std::vector<int64_t> &ids = std::next(groups.begin(), g)->second;
             fill_stats(dims[g], specs[g].Q, h.data(), ids.data(), stats);

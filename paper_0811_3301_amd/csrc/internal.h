@@ -16,6 +16,8 @@ constexpr unsigned long long kNoKey = ~0ull;  // larger than every (distance, in
 constexpr size_t kLdsBudget = 65536;          // dynamic LDS per workgroup used by any kernel
 constexpr int kLaneMaxW = 63;                 // widest band (half-width) of the lane-per-pair DTW
 constexpr int kLbiRegMaxW = 52;               // widest band of the register-state LB_Improved
+constexpr int kCounters = 5;                  // per-query counters of a search: cnt1, cnt2, rescnt, abandoned, cnt0
+constexpr int kPdParts = 8;                   // parts d of the piecewise-sum cover (Sec. 9)
 
 // Launch wrappers.  Every pointer is device memory; all launches go to `s`.
 // Each returns hipSuccess or the launch error.
@@ -30,8 +32,8 @@ hipError_t launch_pack(const float *rows, int64_t N, int n, float4 *il, hipStrea
 
 // Envelope of B series (rows of length n) into rows of stride ldo; rows b in [B, Bpad) and
 // columns i in [n, ldo) are filled with U = +inf, L = -inf when ldo > n or Bpad > B.
-// keys0 / keys1, when given, receive "no key" in their first B entries; counts4 ([4][B]), when
-// given, receives 0 in all its entries.
+// keys0 / keys1, when given, receive "no key" in their first B entries; counts4 ([kCounters][B]),
+// when given, receives 0 in all its entries.
 hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w, float *U, float *L, int ldo,
                            hipStream_t s, unsigned long long *keys0 = nullptr, unsigned long long *keys1 = nullptr,
                            int *counts4 = nullptr);
@@ -67,6 +69,17 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t 
 hipError_t launch_fill_i32(int *p, int v, int64_t count, hipStream_t s);
 hipError_t launch_iota_i32(int *p, int64_t count, hipStream_t s);  // p[i] = i
 
+// Piecewise sums (Sec. 9) over the kPdParts parts of the cover, in fp64: pd [N][kPdParts] of
+// the rows of a database; qpd [Q][2][kPdParts] of query envelopes (U sums, then L sums).
+hipError_t launch_pd_rows(const float *rows, int64_t N, int n, double *pd, hipStream_t s);
+hipError_t launch_pd_query(const float *U, const float *L, int ldq, int64_t Q, int n, double *qpd, hipStream_t s);
+// Pass 0: the piecewise-sum bound of every candidate against Q queries into out[q][c] (pow
+// domain, or root form with root), +inf in padding columns [N, ldo) when pad_inf; with wmin,
+// the smallest (bound, index) key of every 64 candidates, wmin[q][v] for v < pd_scan_waves(N).
+int64_t pd_scan_waves(int64_t N);
+hipError_t launch_pd_scan(int p, const double *pd, int64_t N, int n, const double *qpd, int64_t Q, float *out,
+                          int64_t ldo, bool pad_inf, bool root, unsigned long long *wmin, hipStream_t s);
+
 // Pair list description for the persistent second-pass and DTW kernels.
 struct PairList {
     const int *list;     // [Q][ldl] candidate ids, or nullptr for "candidate = position"
@@ -92,6 +105,14 @@ hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, 
                       int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
                       bool pipeline, hipStream_t s);
+
+// LB_Keogh^p of the pairs of pl (the pass-0 survivors), reading each candidate's row: S1[q][c]
+// receives the bound; pairs with key(S1, c) < thr[q] are appended to list1/cnt1.  Items hold
+// lbk_gather_batch() pairs; prefix is launch_items_prefix over pl.cnt.
+int lbk_gather_batch();
+hipError_t launch_lbk_gather(int p, const float *rows, int n, QueryData qd, PairList pl, const long long *prefix,
+                             int64_t Q, int num_cu, float *S1, int64_t ldS, const unsigned long long *thr, int *list1,
+                             int64_t ldl1, int *cnt1, hipStream_t s);
 
 // Banded DTW over a pair list.  best (k = 1): per-query best key, updated by atomicMin and used
 // for early abandoning.  thr/res/rescnt (k > 1): keys below thr[q] are appended to res[q].

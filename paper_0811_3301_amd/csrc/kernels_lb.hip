@@ -46,7 +46,7 @@ hipError_t launch_pack(const float *rows, int64_t N, int n, float4 *il, hipStrea
 // window is cut by the series end inside one block.
 // Narrow bands (2w+1 <= kDirectWindow) take the window maximum and minimum of every output
 // directly, one output per thread, from the series in LDS: the plain definition, with no
-// serial walk.  keys0 / keys1 (optional) are set to "no key" and counts4 (optional, [4][B])
+// serial walk.  keys0 / keys1 (optional) are set to "no key" and counts4 (optional, [kCounters][B])
 // to 0 for the B real rows, so a search needs no separate fill launches for its best-so-far
 // and threshold keys and its per-query counters.
 constexpr int kDirectWindow = 128;
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_envelope(const float *__restrict__ y, i
         if (keys0) keys0[b] = kNoKey;
         if (keys1) keys1[b] = kNoKey;
     }
-    if (counts4 && threadIdx.x < 4) counts4[threadIdx.x * B + b] = 0;
+    if (counts4 && threadIdx.x < kCounters) counts4[threadIdx.x * B + b] = 0;
     const float *yb = y + b * (int64_t)n;
     float *gmax = sm, *gmin = sm + n, *hmax = sm + 2 * n, *hmin = sm + 3 * n;
     // The series is first copied into hmin by the whole block (coalesced), so the reads below

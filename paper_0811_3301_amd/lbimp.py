@@ -29,7 +29,7 @@ _i32 = ctypes.c_int32
 
 class LbimpStats(ctypes.Structure):
     _fields_ = [("candidates", _i64), ("seeded", _i64), ("pruned_keogh", _i64), ("pruned_improved", _i64),
-                ("dtw_started", _i64), ("dtw_abandoned", _i64)]
+                ("dtw_started", _i64), ("dtw_abandoned", _i64), ("pruned_pd", _i64)]
 
 
 STATS_FIELDS = [f for f, _ in LbimpStats._fields_]
@@ -50,6 +50,7 @@ SIGNATURES = {
     "lbimp_envelope": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _vp, _vp]),
     "lbimp_lb_keogh": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, _i32, _vp]),
     "lbimp_db_lb_keogh": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _vp]),
+    "lbimp_db_pd_bound": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _vp]),
     "lbimp_lb_improved": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, _vp, _i32, _i32, _vp]),
     "lbimp_dtw_band": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _i32, _i32, _vp]),
     "lbimp_dtw_pairs": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _vp]),
@@ -66,7 +67,7 @@ SIGNATURES = {
     "lbimp_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32)]),
     "lbimp_ctx_copy_tuning": (ctypes.c_int, [_vp, _vp]),
 }
-TUNE_KNOBS = ("seeds", "sweep_shape", "lbi_pipeline", "dtw_group", "seed_lane", "cascade")
+TUNE_KNOBS = ("seeds", "sweep_shape", "lbi_pipeline", "dtw_group", "seed_lane", "cascade", "pd")
 
 _lib = None
 
@@ -223,6 +224,16 @@ def lbimp_db_lb_keogh(ctx: Ctx, db: Db, U: torch.Tensor, L: torch.Tensor, p: int
     out = _out(out, (Q, db.N), torch.float32, U)
     _check(_lib.lbimp_db_lb_keogh(ctx.sync_stream(), db.h, _dev(U2, "U"), _dev(L.reshape(-1, db.n), "L"), Q, _p(p),
                                   _dev(out, "lb")), "lbimp_db_lb_keogh")
+    return out
+
+
+def lbimp_db_pd_bound(ctx: Ctx, db: Db, U: torch.Tensor, L: torch.Tensor, p, out=None):
+    """Piecewise-sum lower bound (Sec. 9) of every database row for Q envelopes: [Q][N]."""
+    U2 = U.reshape(-1, db.n)
+    Q = U2.shape[0]
+    out = _out(out, (Q, db.N), torch.float32, U)
+    _check(_lib.lbimp_db_pd_bound(ctx.sync_stream(), db.h, _dev(U2, "U"), _dev(L.reshape(-1, db.n), "L"), Q, _p(p),
+                                  _dev(out, "lb")), "lbimp_db_pd_bound")
     return out
 
 

@@ -204,6 +204,50 @@ def test_dtw_pairs(L, ctx, N, n, w, p):
     assert_close(d, rt(D, p), scale, "dtw_pairs")
 
 
+# ------------------------------------------------------------------ piecewise-sum bound (Sec. 9)
+@pytest.mark.parametrize("N,n", [(1, 1), (63, 7), (300, 8), (65, 131), (1000, 256), (70, 1000)])
+@pytest.mark.parametrize("p", [1, 2, INF])
+def test_db_pd_bound(L, ctx, N, n, p):
+    _say(f"db_pd_bound N={N} n={n} p={p}")
+    X = walks(N, n, 32)
+    Ys = walks(3, n, 33)
+    w = max(0, n // 10)
+    db = L.Db(ctx, to_dev(X))
+    env = [R.envelope_naive(Ys[q], w) for q in range(3)]
+    lb = L.lbimp_db_pd_bound(ctx, db, to_dev(np.stack([e[0] for e in env])), to_dev(np.stack([e[1] for e in env])),
+                             p).cpu().numpy()
+    for q in range(3):
+        want = rt(R.pd_bound_pow_many(X, env[q][0], env[q][1], p), p)
+        assert_close(lb[q], want, lp_scale(X, Ys[q], p), f"pd_bound q={q}")
+        s1, _ = native.lb_many(X, Ys[q], w, p)
+        assert np.all(lb[q] <= rt(s1, p) * (1 + 1e-6) + 1e-6)  # below LB_Keogh
+    db.close()
+
+
+@pytest.mark.parametrize("mode", ["keogh", "improved"])
+@pytest.mark.parametrize("p,k", [(1, 1), (2, 3), (INF, 2), (1, 10)])
+@pytest.mark.parametrize("n,w", [(128, 13), (200, 80), (37, 4)])
+def test_nn_search_pd_prefilter(L, ctx, mode, p, k, n, w):
+    """Pass 0 (piecewise sums) ahead of LB_Keogh: the same answers, bit for bit, as without it,
+    matching the oracle; the pass prunes on random walks; counts stay within the invariants."""
+    _say(f"nn_search pd_prefilter mode={mode} p={p} k={k} n={n} w={w}")
+    X = walks(3000, n, 34)
+    Ys = walks(7, n, 35)
+    db = L.Db(ctx, to_dev(X))
+    Yd = to_dev(Ys)
+    ri, rd, _ = L.lbimp_nn_search(ctx, db, Yd, w, p, k, mode)
+    L.lbimp_ctx_set_option(ctx, "pd_prefilter", 1)
+    try:
+        idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, p, k, mode)
+    finally:
+        L.lbimp_ctx_set_option(ctx, "pd_prefilter", 0)
+    assert torch.equal(idx, ri) and torch.equal(dist, rd)
+    check_knn(X, Ys, w, p, k, idx.cpu().numpy(), dist.cpu().numpy(), f"pd {mode} p={p} k={k}")
+    check_stats(X, Ys, w, p, st, mode, pd=True)
+    assert st[:, 6].sum() > 0
+    db.close()
+
+
 # ------------------------------------------------------------------ nearest-neighbour search
 def oracle_knn(X, Ys, w, p, k):
     idx, dist = native.nn_bruteforce(X, Ys, R.effective_band(X.shape[1], w), p, k)
@@ -266,25 +310,33 @@ def check_golden(name, X, Ys, w, p, gidx, gdist):
     return rel
 
 
-def check_stats(X, Ys, w, p, st, mode):
+def check_stats(X, Ys, w, p, st, mode, pd=False):
     """Counts relative to the exact final threshold b*: the device threshold is never below b*,
-    so it prunes no candidate whose bound is below b* (up to float32 rounding)."""
+    so it prunes no candidate whose bound is below b* (up to float32 rounding).  The bounds are
+    nested (P_d <= LB_Keogh <= LB_Improved), so each pass's cumulative count is checked against
+    its own bound."""
     N, n = X.shape
     wb = R.effective_band(n, w)
     for q in range(Ys.shape[0]):
-        cand, seeded, pk, pi, started, aband = st[q]
+        cand, seeded, pk, pi, started, aband, ppd = st[q]
         assert cand == N
-        assert seeded + pk + pi + (started - seeded) == N
+        assert seeded + ppd + pk + pi + (started - seeded) == N
         assert 0 <= aband <= started
         if mode == "brute":
-            assert started == N and pk == pi == 0
+            assert started == N and pk == pi == ppd == 0
             continue
+        if not pd:
+            assert ppd == 0
         D = native.dtw_pow_many(X, Ys[q], wb, p)
         s1, s2 = native.lb_many(X, Ys[q], wb, p)
         bstar = D.min()
         slack = 1 + 1e-4
-        assert pk <= np.sum(s1 * slack >= bstar)
-        assert pk + pi <= np.sum(s2 * slack >= bstar)
+        if pd:
+            U, Lo = R.envelope_naive(Ys[q], wb)
+            b0 = R.pd_bound_pow_many(X, U, Lo, p)
+            assert ppd <= np.sum(b0 * slack >= bstar)
+        assert ppd + pk <= np.sum(s1 * slack >= bstar)
+        assert ppd + pk + pi <= np.sum(s2 * slack >= bstar)
         if mode == "keogh":
             assert pi == 0
 

@@ -58,7 +58,7 @@ def _alone(L, ctx, handles, db_of, w, Ys, p, k, mode, n_of):
     Q = len(db_of)
     idx = np.zeros((Q, k), np.int64)
     dist = np.zeros((Q, k), np.float32)
-    st = np.zeros((Q, 6), np.int64)
+    st = np.zeros((Q, 7), np.int64)
     keys = sorted({(int(b), min(int(wq), n_of[b] - 1)) for b, wq in zip(db_of, w)})
     for b, wb in keys:
         qs = [q for q in range(Q) if db_of[q] == b and min(int(w[q]), n_of[b] - 1) == wb]
