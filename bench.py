@@ -149,16 +149,27 @@ def stage_profile(L, ctx, db, Yd, w, p, mode, steps):
     return {k: v / steps for k, v in acc.items()}
 
 
-def single_query_lb_gbps(L, ctx, steps=20):
+def big_database(L, ctx):
+    """The 1,000,000 x 128 random-walk database of the serving workload (512 MB, twice the
+    256 MB Infinity Cache), resident on the device."""
+    import torch
+    from paper_0811_3301_amd import gen
+    X = torch.from_numpy(gen.random_walk(1_000_000, 128, gen.rng(5, gen.ROLE_DB)).astype(np.float32)).cuda()
+    db = L.Db(ctx, X)
+    del X
+    torch.cuda.synchronize()
+    return db
+
+
+def single_query_lb_gbps(L, ctx, steps=20, db=None):
     """LB_Keogh of one query over a 1,000,000 x 128 random-walk database (512 MB, larger than
     the 256 MB Infinity Cache): the HBM-bound form of the first pass."""
     import torch
     from paper_0811_3301_amd import gen
     N, n, w = 1_000_000, 128, 13
-    g = gen.rng(5, gen.ROLE_DB)
-    X = torch.from_numpy(gen.random_walk(N, n, g).astype(np.float32)).cuda()
-    db = L.Db(ctx, X)
-    del X
+    own = db is None
+    if own:
+        db = big_database(L, ctx)
     y = torch.from_numpy(gen.random_walk(1, n, gen.rng(5, gen.ROLE_QUERY)).astype(np.float32)).cuda()
     U, Lo = L.lbimp_envelope(ctx, y, w)
     out = torch.empty((1, N), dtype=torch.float32, device="cuda")
@@ -173,9 +184,46 @@ def single_query_lb_gbps(L, ctx, steps=20):
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    db.close()
+    if own:
+        db.close()
     nbytes = N * n * 4
     return dict(db_bytes=nbytes, ms=ms, gbps=nbytes / ms / 1e6, frac_hbm=nbytes / ms / 1e6 / HBM_PEAK_GBPS)
+
+
+def pd_bench(L, ctx, db, steps=20, qs=(1, 4, 16)):
+    """Pass 0 (piecewise sums, Sec. 9) ahead of LB_Keogh on the 512 MB database, w = 13, p = 1,
+    1-NN, two-pass search of Q queries per call: the time per call and the database bytes the
+    first passes read with and without it, at identical results."""
+    import torch
+    from paper_0811_3301_amd import gen
+    N, n, w = 1_000_000, 128, 13
+    ctx = L.Ctx(0)  # untuned: both forms run with the default choices
+    Y = torch.from_numpy(gen.random_walk(max(qs), n, gen.rng(5, gen.ROLE_QUERY, 7)).astype(np.float32)).cuda()
+    out = dict(workload="1,000,000 x 128 random walks (512 MB), w=13, p=1, 1-NN, two-pass search",
+               pass0_bytes_per_candidate=64)
+    for Q in qs:
+        Yq = Y[:Q].contiguous()
+        r = {}
+        for pd in (0, 1):
+            L.lbimp_ctx_set_option(ctx, "pd_prefilter", pd)
+            t = time_mode(L, ctx, db, Yq, w, 1, "improved", steps, 2)
+            _, _, st = L.lbimp_nn_search(ctx, db, Yq, w, 1, 1, "improved")
+            st_ms = stage_profile(L, ctx, db, Yq, w, 1, "improved", 5)
+            c0 = float((N - st[:, 1] - st[:, 6]).sum())  # pass-0 survivors (all candidates without pass 0)
+            # bytes of the database read by the passes before LB_Improved: the sweep reads every
+            # row once per query group of 16; pass 0 reads the sums, then the rows of its survivors
+            first = (N * 8 * 8 * -(-Q // 16) + c0 * n * 4) if pd else N * n * 4 * -(-Q // 16)
+            r["pd" if pd else "sweep"] = dict(ms_per_call=t["ms_per_step"], qps=Q / t["ms_per_step"] * 1e3,
+                                              first_pass_db_bytes=first, stage_ms=st_ms,
+                                              pass0_survivor_fraction=c0 / (N * Q) if pd else None,
+                                              idx=t["idx"].tolist())
+        L.lbimp_ctx_set_option(ctx, "pd_prefilter", 0)
+        r["same_results"] = r["pd"].pop("idx") == r["sweep"].pop("idx")
+        r["speedup"] = r["sweep"]["ms_per_call"] / r["pd"]["ms_per_call"]
+        out[f"Q{Q}"] = r
+    torch.cuda.synchronize()
+    ctx.close()
+    return out
 
 
 def cpu_model():
@@ -413,7 +461,7 @@ def main():
     ap.add_argument("--no-triangle", action="store_true", help="skip the App. B triangle-inequality workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
-    ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle"),
+    ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle", "pd"),
                     help="run only the uneven-batch or the serving measurement and print its JSON (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -440,9 +488,16 @@ def main():
     if args.only == "shapes":
         print(json.dumps(shape_bench(L, args.steps)), flush=True)
         return
-    if args.only in ("triangle", "lbsingle"):
+    if args.only in ("triangle", "lbsingle", "pd"):
         ctx = L.Ctx(0)
-        out = triangle_bench(L, ctx) if args.only == "triangle" else single_query_lb_gbps(L, ctx, args.steps)
+        if args.only == "triangle":
+            out = triangle_bench(L, ctx)
+        elif args.only == "lbsingle":
+            out = single_query_lb_gbps(L, ctx, args.steps)
+        else:
+            big = big_database(L, ctx)
+            out = pd_bench(L, ctx, big, args.steps)
+            big.close()
         print(json.dumps(out), flush=True)
         ctx.close()
         return
@@ -508,10 +563,14 @@ def main():
         modes["brute"]["dtw_cells_per_s"] = cells / t
         modes["brute"]["dtw_frac_of_alu_peak"] = DTW_INSTR_PER_CELL * cells / t / VALU_PEAK
 
-    lbg = None
+    lbg = pdb = None
     if not args.quick:
         log("single-query LB_Keogh sweep over a 512 MB database")
-        lbg = single_query_lb_gbps(L, ctx)
+        big = big_database(L, ctx)
+        lbg = single_query_lb_gbps(L, ctx, db=big)
+        log("pass 0 (piecewise sums) against the sweep on the 512 MB database")
+        pdb = pd_bench(L, ctx, big)
+        big.close()
 
     ragged = None
     if not (args.quick or args.no_ragged):
@@ -568,6 +627,7 @@ def main():
         "stage_ms_p1": stages,
         "accuracy_vs_oracle": accuracy,
         "lb_single_query_hbm": lbg,
+        "pd_prefilter": pdb,
         "batch_latency_ms": dict(p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99))),
         "ragged": ragged,
         "shapes": shapes,

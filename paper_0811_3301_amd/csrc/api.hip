@@ -363,14 +363,14 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, sp.kq, b.thr, s));
         stage(4);
         if (d.pd) {
-            // the pass-0 survivors, then LB_Keogh of their rows (pass 1), which keeps its own survivors
+            // the pass-0 survivors, then LB_Keogh of their rows (pass 1) over their S1 entries; the
+            // others keep their pass-0 bound, at or above the threshold
             HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list0, N, cnt0, s));
             HIPTRY(launch_items_prefix(cnt0, 0, Q, lbk_gather_batch(), b.prefix, s));
             HIPTRY(launch_lbk_gather(p, db->rows, n, qd, PairList{b.list0, N, cnt0, 0}, b.prefix, Q, grid, b.S1, d.Np,
-                                     T, b.list1, N, cnt1, s));
-        } else {
-            HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
+                                     s));
         }
+        HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
         stage(5);
         PairList dl{b.list1, N, cnt1, 0};
         if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)

@@ -107,12 +107,11 @@ hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, 
                       bool pipeline, hipStream_t s);
 
 // LB_Keogh^p of the pairs of pl (the pass-0 survivors), reading each candidate's row: S1[q][c]
-// receives the bound; pairs with key(S1, c) < thr[q] are appended to list1/cnt1.  Items hold
-// lbk_gather_batch() pairs; prefix is launch_items_prefix over pl.cnt.
+// receives the bound.  Items hold lbk_gather_batch() pairs; prefix is launch_items_prefix over
+// pl.cnt.
 int lbk_gather_batch();
 hipError_t launch_lbk_gather(int p, const float *rows, int n, QueryData qd, PairList pl, const long long *prefix,
-                             int64_t Q, int num_cu, float *S1, int64_t ldS, const unsigned long long *thr, int *list1,
-                             int64_t ldl1, int *cnt1, hipStream_t s);
+                             int64_t Q, int num_cu, float *S1, int64_t ldS, hipStream_t s);
 
 // Banded DTW over a pair list.  best (k = 1): per-query best key, updated by atomicMin and used
 // for early abandoning.  thr/res/rescnt (k > 1): keys below thr[q] are appended to res[q].

@@ -164,19 +164,20 @@ hipError_t launch_pd_scan(int p, const double *pd, int64_t N, int n, const doubl
 }
 
 // ------------------------------------------------------------------ LB_Keogh of the survivors
-// One wave per item of G pairs of one query (the pass-0 survivors of list0).  The lanes walk a
-// candidate's row together, 64 consecutive elements per load, with the query envelope in LDS;
-// the G rows' loads of one 64-element chunk are issued before any is used.  The per-lane sums
-// are combined across the wave, S1[q][c] receives LB_Keogh^p (read later by LB_Improved and
-// the DTW), and the pairs whose key is below the threshold are appended to list1.
+// One wave per item of G = 8 pairs of one query (the pass-0 survivors of list0).  The lanes walk
+// a candidate's row together, 64 consecutive elements per load, with the query envelope in
+// LDS; the G rows' loads of one 64-element chunk are issued before any is used.  The G per-lane
+// sums are combined across the wave by a transposing butterfly -- at each of the steps 32, 16, 8
+// a lane keeps half of its values and adds its partner's copies of them, so after three steps
+// lane l holds pair l/8 summed over 8 lanes -- then three plain steps finish the sums: 10 lane
+// exchanges instead of 6 per pair.  S1[q][c] receives LB_Keogh^p (the compaction that follows
+// reads it, as do LB_Improved and the DTW).
 constexpr int kGatherPairs = 8;
 
 template <int P>
 __global__ __launch_bounds__(64) void k_lbk_gather(const float *__restrict__ rows, int n, QueryData qd, PairList pl,
                                                     const long long *__restrict__ prefix, int64_t Q,
-                                                    float *__restrict__ S1, int64_t ldS,
-                                                    const unsigned long long *__restrict__ thr,
-                                                    int *__restrict__ list1, int64_t ldl1, int *__restrict__ cnt1) {
+                                                    float *__restrict__ S1, int64_t ldS) {
     extern __shared__ float sm[];
     float *sU = sm, *sL = sm + n;
     const int lane = threadIdx.x;
@@ -215,39 +216,45 @@ __global__ __launch_bounds__(64) void k_lbk_gather(const float *__restrict__ row
             for (int g = 0; g < kGatherPairs; ++g)
                 if (i < n) acc[g] = pacc<P>(acc[g], v[g] - __builtin_amdgcn_fmed3f(v[g], l, u));
         }
-        float mine = 0.f;  // lane g ends up holding the whole sum of pair g
+        float v4[4], v2[2];
+        {
+            const bool up = lane & 32;
 #pragma unroll
-        for (int g = 0; g < kGatherPairs; ++g) {
-            float a = acc[g];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) a = pjoin<P>(a, __shfl_xor(a, off));
-            if (lane == g) mine = a;
+            for (int t = 0; t < 4; ++t) {
+                const float send = up ? acc[t] : acc[t + 4], keep = up ? acc[t + 4] : acc[t];
+                v4[t] = pjoin<P>(keep, __shfl_xor(send, 32));
+            }
         }
+        {
+            const bool up = lane & 16;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const float send = up ? v4[t] : v4[t + 2], keep = up ? v4[t + 2] : v4[t];
+                v2[t] = pjoin<P>(keep, __shfl_xor(send, 16));
+            }
+        }
+        const bool up = lane & 8;
+        float v1 = pjoin<P>(up ? v2[1] : v2[0], __shfl_xor(up ? v2[0] : v2[1], 8));
+        v1 = pjoin<P>(v1, __shfl_xor(v1, 4));
+        v1 = pjoin<P>(v1, __shfl_xor(v1, 2));
+        v1 = pjoin<P>(v1, __shfl_xor(v1, 1));
+        // lanes 8g .. 8g+7 now hold the sum of pair g
         int cm = -1;
 #pragma unroll
         for (int g = 0; g < kGatherPairs; ++g)
-            if (lane == g) cm = c[g];
-        if (cm >= 0) S1[q * ldS + cm] = mine;
-        const bool keep = cm >= 0 && make_key(mine, cm) < thr[q];
-        const unsigned long long m = __ballot(keep);
-        if (m) {
-            int pos = 0;
-            if (lane == 0) pos = atomicAdd(&cnt1[q], __popcll(m));
-            pos = __shfl(pos, 0);
-            if (keep) list1[q * ldl1 + pos + __popcll(m & ((1ull << lane) - 1ull))] = cm;
-        }
+            if ((lane >> 3) == g) cm = c[g];
+        if ((lane & 7) == 0 && cm >= 0) S1[q * ldS + cm] = v1;
     }
 }
 
 int lbk_gather_batch() { return kGatherPairs; }
 
 hipError_t launch_lbk_gather(int p, const float *rows, int n, QueryData qd, PairList pl, const long long *prefix,
-                             int64_t Q, int num_cu, float *S1, int64_t ldS, const unsigned long long *thr, int *list1,
-                             int64_t ldl1, int *cnt1, hipStream_t s) {
+                             int64_t Q, int num_cu, float *S1, int64_t ldS, hipStream_t s) {
     const size_t lds = sizeof(float) * 2 * (size_t)n;
 #define LBIMP_GATHER(PP)                                                                                              \
     hipLaunchKernelGGL(k_lbk_gather<PP>, dim3(persistent_grid(k_lbk_gather<PP>, lds, num_cu)), dim3(64), lds, s, rows, \
-                       n, qd, pl, prefix, Q, S1, ldS, thr, list1, ldl1, cnt1)
+                       n, qd, pl, prefix, Q, S1, ldS)
     if (p == 1)
         LBIMP_GATHER(1);
     else if (p == 2)
