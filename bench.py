@@ -359,6 +359,45 @@ def shape_bench(L, steps):
     return out
 
 
+def lbi_abandon_bench(L, steps=10):
+    """Early abandoning inside LB_Improved (the paper's Sec. 10 experiment on the CPU measured
+    under 1%): the two-pass search with it off and on, untuned, on the headline workload (the
+    register kernel, w = 26) and on wide bands (the wave-per-pair kernel: 20,000 x 1024 random
+    walks, 64 queries, w = 102 and 205)."""
+    import torch
+    from paper_0811_3301_amd import gen
+    out = {}
+    cases = (("rw256_w26", "rw256", 26), ("rw1024_w102", None, 102), ("rw1024_w205", None, 205))
+    ctx = L.Ctx(0)
+    cache = {}
+    for name, wl, w in cases:
+        if wl not in cache:
+            if wl:
+                db64, qs64 = gen.make_workload(wl)
+            else:
+                db64 = gen.random_walk(20_000, 1024, gen.rng(4, gen.ROLE_DB, 4))
+                qs64 = gen.random_walk(64, 1024, gen.rng(4, gen.ROLE_QUERY, 9))
+            cache[wl] = (L.Db(ctx, torch.from_numpy(db64.astype(np.float32)).cuda()),
+                         torch.from_numpy(qs64.astype(np.float32)).cuda())
+        db, Yd = cache[wl]
+        r = {}
+        for ab in (0, 1):
+            L.lbimp_ctx_set_option(ctx, "lbi_abandon", ab)
+            t = time_mode(L, ctx, db, Yd, w, 1, "improved", steps, 1)
+            st_ms = stage_profile(L, ctx, db, Yd, w, 1, "improved", 3)
+            r["on" if ab else "off"] = dict(ms_per_call=t["ms_per_step"], lb_improved_ms=st_ms["lb_improved"],
+                                            idx=t["idx"].tolist())
+        L.lbimp_ctx_set_option(ctx, "lbi_abandon", 0)
+        r["same_results"] = r["on"].pop("idx") == r["off"].pop("idx")
+        r["lb_improved_speedup"] = r["off"]["lb_improved_ms"] / r["on"]["lb_improved_ms"]
+        out[name] = r
+    torch.cuda.synchronize()
+    for db, _ in cache.values():
+        db.close()
+    ctx.close()
+    return out
+
+
 def triangle_bench(L, ctx, count=100_000, n=100, steps=5):
     """App. B: 100,000 triples (x, y, z) of 100-sample random walks (and white noise),
     unconstrained DTW_1 and DTW_2 (w = n), C = DTW(x,z) / (DTW(x,y) + DTW(y,z)); one
@@ -461,7 +500,7 @@ def main():
     ap.add_argument("--no-triangle", action="store_true", help="skip the App. B triangle-inequality workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
-    ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle", "pd"),
+    ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle", "pd", "abandon"),
                     help="run only the uneven-batch or the serving measurement and print its JSON (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -487,6 +526,9 @@ def main():
         return
     if args.only == "shapes":
         print(json.dumps(shape_bench(L, args.steps)), flush=True)
+        return
+    if args.only == "abandon":
+        print(json.dumps(lbi_abandon_bench(L, args.steps)), flush=True)
         return
     if args.only in ("triangle", "lbsingle", "pd"):
         ctx = L.Ctx(0)
@@ -587,6 +629,11 @@ def main():
         log("serving loop")
         serving = serving_bench(L, rates=(1_000, 2_000, 5_000, 10_000, 20_000, 35_000, 50_000))
 
+    lbi_ab = None
+    if not args.quick:
+        log("early abandoning inside LB_Improved, off and on")
+        lbi_ab = lbi_abandon_bench(L)
+
     triangle = None
     if not (args.quick or args.no_triangle):
         log("App. B triangle-inequality workload (100000 triples, n=100, unconstrained DTW)")
@@ -633,6 +680,7 @@ def main():
         "shapes": shapes,
         "serving": serving,
         "triangle": triangle,
+        "lbi_abandon": lbi_ab,
     }
     print(json.dumps(out), flush=True)
     db.close()

@@ -107,7 +107,11 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *                   Sec. 9 (d = 8 part sums per series, 64 bytes per candidate), seed the
  *                   threshold from its smallest values, and compute LB_Keogh only of the
  *                   candidates it keeps, reading their rows; it pays where the first pass is
- *                   bound by database reads (a few queries per database sweep).
+ *                   bound by database reads (a few queries per database sweep);
+ *   "lbi_abandon"   0/1 (default 0): early abandoning inside the LB_Improved pass (Sec. 10 of
+ *                   the paper tried it on the CPU): a wave stops a pair's sum once it reaches the
+ *                   threshold -- the register kernel when all 64 pairs of a wave have, the
+ *                   wave-per-pair kernel of wide bands before the second half of a pair's sum.
  * Returns LBIMP_E_INVALID for an unknown name or an out-of-range value. */
 int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
 
@@ -229,8 +233,9 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
  * "autotune" set, those calls tune a shape they meet for the first time by themselves.
  * choice: host [LBIMP_TUNE_KNOBS] or NULL, receives {seeds, sweep_shape, lbi_pipeline,
  * survivors' DTW group-per-pair, seeding DTW lane-per-pair, abandon bound with the LB_Keogh
- * tail, pass 0 with the piecewise-sum bound}.  Waits for the stream. */
-#define LBIMP_TUNE_KNOBS 7
+ * tail, pass 0 with the piecewise-sum bound, early abandoning in LB_Improved}.  Waits for the
+ * stream. */
+#define LBIMP_TUNE_KNOBS 8
 int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                    int32_t k, int32_t mode, int32_t *choice);
 

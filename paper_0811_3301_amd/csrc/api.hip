@@ -113,6 +113,7 @@ struct lbimp_ctx {
     bool use_graph = true;         // option "graph" (lbimp_nn_search_ragged)
     int ragged_streams = kPoolStreams;  // option "ragged_streams"
     bool pd_prefilter = false;          // option "pd_prefilter"
+    bool lbi_abandon = false;           // option "lbi_abandon"
     // ragged batches: stream pool, captured graph, pinned staging of the grouping metadata
     hipStream_t graph_stream = nullptr;
     hipStream_t pool[kPoolStreams] = {};
@@ -206,6 +207,7 @@ struct Knobs {
     bool seed_lane;     // seeding DTWs with a lane per pair (else a group of lanes per pair)
     bool cascade;       // abandon on the row minimum plus the LB_Keogh terms still to come
     bool pd = false;    // pass 0: piecewise-sum bound of every candidate, LB_Keogh only of its survivors
+    bool lbi_abandon = false;  // early abandoning inside the LB_Improved pass
 };
 
 struct SearchSpec {  // Q queries of one length against one database
@@ -376,7 +378,7 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
         if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
             HIPTRY(launch_items_prefix(cnt1, 0, Q, d.WL, b.prefix, s));
             HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, b.S1, d.Np, b.prefix, Q, nullptr, grid,
-                              T, b.list2, N, cnt2, nullptr, sp.kn.lbi_pipeline, s));
+                              T, b.list2, N, cnt2, nullptr, sp.kn.lbi_pipeline, sp.kn.lbi_abandon, s));
             dl = PairList{b.list2, N, cnt2, 0};
         }
         stage(6);
@@ -396,7 +398,8 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
 }
 
 static Knobs ctx_knobs(const lbimp_ctx *ctx) {
-    return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false, true, ctx->pd_prefilter};
+    return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false, true, ctx->pd_prefilter,
+                 ctx->lbi_abandon};
 }
 
 static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int mode) {
@@ -404,12 +407,12 @@ static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int
 }
 
 static Knobs knobs_of(const std::array<int, kTuneKnobs> &v) {
-    return Knobs{v[0], v[2] != 0, v[1], v[3] != 0, v[4] != 0, v[5] != 0, v[6] != 0};
+    return Knobs{v[0], v[2] != 0, v[1], v[3] != 0, v[4] != 0, v[5] != 0, v[6] != 0, v[7] != 0};
 }
 
 static std::array<int, kTuneKnobs> knob_values(const Knobs &k) {
     return {k.seeds, k.sweep_shape, k.lbi_pipeline ? 1 : 0, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0,
-            k.cascade ? 1 : 0, k.pd ? 1 : 0};
+            k.cascade ? 1 : 0, k.pd ? 1 : 0, k.lbi_abandon ? 1 : 0};
 }
 
 // The tuned choice for this batch shape if there is one, else the context's options.
@@ -540,6 +543,11 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     if (improved && wb <= kLbiRegMaxW) {
         Knobs kn = best;
         kn.lbi_pipeline = !kn.lbi_pipeline;
+        if (int r = consider(kn)) return r;
+    }
+    if (improved) {
+        Knobs kn = best;
+        kn.lbi_abandon = !kn.lbi_abandon;
         if (int r = consider(kn)) return r;
     }
     if (!brute) {
@@ -781,6 +789,8 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         ctx->ragged_streams = (int)value;
     } else if (!strcmp(name, "pd_prefilter")) {
         ctx->pd_prefilter = value != 0;
+    } else if (!strcmp(name, "lbi_abandon")) {
+        ctx->lbi_abandon = value != 0;
     } else if (!strcmp(name, "sweep_shape")) {
         if (value < 0 || value > 5) return fail(LBIMP_E_INVALID, "sweep_shape must be in [0, 5]");
         ctx->sweep_shape = (int)value;
@@ -961,7 +971,7 @@ int lbimp_lb_improved(lbimp_ctx *ctx, const float *x, int64_t N, int32_t n, cons
     QueryData qd{y, n, U, L, n};
     PairList pl{nullptr, 0, nullptr, N};
     HIPTRY(launch_lbi(p, x, (int64_t)N * n * 4, n, wb, qd, pl, S1, N, prefix, 1, ctr, persistent_grid(ctx), nullptr, nullptr, 0,
-                      nullptr, lb, ctx->lbi_pipeline, s));
+                      nullptr, lb, ctx->lbi_pipeline, false, s));
     return LBIMP_OK;
 }
 
@@ -1202,7 +1212,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         mix((uint64_t)(specs[g].k * 2 + (plan.mixed_k[g] ? 1 : 0)));
         const Knobs &kn = specs[g].kn;
         mix((uint64_t)(kn.seeds * 1000000 + kn.sweep_shape * 10000 + kn.lbi_pipeline * 1000 + kn.dtw_group * 100 +
-                       kn.seed_lane * 10 + kn.cascade + (kn.pd ? 100000000 : 0)));
+                       kn.seed_lane * 10 + kn.cascade + (kn.pd ? 100000000 : 0) + (kn.lbi_abandon ? 200000000 : 0)));
     }
     if (!ctx->use_graph && width <= 1) {
         if (int r = enqueue_all(ctx->stream)) return r;

@@ -195,6 +195,7 @@ struct LbiArgs {
     int *cnt2;
     float *out_root;
     bool pipeline;  // software-pipelined staging (more registers, fewer exposed load latencies)
+    bool abandon;   // early abandoning: stop once the partial bound reaches the threshold (thr set)
 };
 
 // Wave-per-pair LB_Improved for wide bands (n + w <= 2048, 2w + 1 larger than a lane's slice).

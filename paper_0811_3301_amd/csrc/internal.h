@@ -100,11 +100,13 @@ struct QueryData {
 // (single query).  prefix: items of `lbi_batch(n, w)` pairs; 0 means the per-lane envelope
 // state of this (n, w) does not fit in LDS.  The kernels read prefix (launch_items_prefix
 // over pl.cnt) only when pl.cnt is set; a fixed count per query maps items arithmetically.
+// abandon: stop a pair's sum once it reaches the threshold (register and wave-per-pair kernels;
+// only with thr and without out_root).
 int lbi_batch(int n, int w);
 hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, QueryData qd, PairList pl, const float *S1,
                       int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
-                      bool pipeline, hipStream_t s);
+                      bool pipeline, bool abandon, hipStream_t s);
 
 // LB_Keogh^p of the pairs of pl (the pass-0 survivors), reading each candidate's row: S1[q][c]
 // receives the bound.  Items hold lbk_gather_batch() pairs; prefix is launch_items_prefix over

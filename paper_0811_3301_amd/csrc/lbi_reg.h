@@ -22,6 +22,9 @@ namespace lbimp {
 // in LDS, transposed ([offset][pair]) so each lane reads its own column without bank
 // conflicts.  The staging loads are coalesced: for pair j the wave reads K consecutive floats
 // of row c_j, one per lane, and applies the clamp on the way in.
+// Early abandoning (a.abandon, with a threshold): the bound only grows as terms are added, so a
+// pair is pruned once S1 combined with the terms so far reaches the threshold key; the wave
+// leaves the block loop when every one of its pairs has (a lane alone cannot skip work).
 // Positions e >= n repeat x'[n-1]: every window of an output i < n that reaches past the end
 // contains n-1, so the repeated value changes no maximum or minimum.
 template <int P, int W, bool FIRST, bool PARTIAL>
@@ -72,6 +75,9 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
         const long long j = b * 64 + lane;
         const bool active = j < pair_count(a.pl, q);
         const int c = active ? pair_cand(a.pl, q, j) : 0;
+        const float s1 = active ? a.S1[q * a.ldS + c] : 0.f;
+        const bool abandon = a.abandon && a.thr && !a.out_root;
+        const u64 tq = a.thr ? a.thr[q] : kNoKey;
         float hx[K + 1], hn[K + 1];
 #pragma unroll
         for (int o = 0; o <= K; ++o) {
@@ -145,6 +151,7 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
             } else {
                 lbi_forward<P, W, false, false>(acc, hx, hn, stage, yb, olim, lane);
             }
+            if (abandon && B + 1 < nblk && __ballot(active && make_key(pjoin<P>(s1, acc), c) < tq) == 0) break;
             if (B + 1 < nblk) {  // suffix max/min in place (hx[K], hn[K] stay neutral)
 #pragma unroll
                 for (int o = K - 1; o >= 0; --o) {
@@ -154,7 +161,7 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
                 }
             }
         }
-        const float s2 = pjoin<P>(active ? a.S1[q * a.ldS + c] : 0.f, acc);
+        const float s2 = pjoin<P>(s1, acc);
         if (a.out_root && active) a.out_root[c] = root_p<P>(s2);
         if (a.thr) {
             const bool keep = active && make_key(s2, c) < a.thr[q];

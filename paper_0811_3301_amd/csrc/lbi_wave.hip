@@ -155,6 +155,9 @@ __global__ __launch_bounds__(64) void k_lbi_wave(LbiArgs a, int w) {
         const long long j0 = b * 64;
         const int cnt = (int)min(64ll, (long long)pair_count(a.pl, q) - j0);
         const int c_mine = lane < cnt ? pair_cand(a.pl, q, j0 + lane) : 0;
+        const float s1_mine = lane < cnt ? a.S1[q * a.ldS + c_mine] : 0.f;
+        const bool abandon = a.abandon && a.thr && !a.out_root;
+        const u64 tq = a.thr ? a.thr[q] : kNoKey;
         float s2_mine = 0.f;
         // rows are loaded one pair ahead of their use
         float xr[M];
@@ -172,13 +175,26 @@ __global__ __launch_bounds__(64) void k_lbi_wave(LbiArgs a, int w) {
                 xp[j] = __builtin_amdgcn_fmed3f(xr[j], sLq[j * 64 + lane], sUq[j * 64 + lane]);
             if (t + 1 < cnt) load_row(t + 1);
             float acc = lbi_pass<P, M, true>(xp, yv, sg, sh, w, n, lane, rj);
+            if (abandon) {
+                // early abandoning: the distances of y above the envelope of x' alone may already
+                // take the bound of pair t to its threshold; the pass below it is then skipped
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) acc = pjoin<P>(acc, __shfl_xor(acc, off));
+                const int ct = __shfl(c_mine, t);
+                const float s1t = __shfl(s1_mine, t);
+                if (make_key(pjoin<P>(s1t, acc), ct) >= tq) {
+                    if (lane == t) s2_mine = acc;
+                    continue;
+                }
+                acc = lane == 0 ? acc : (P == kPInf ? acc : 0.f);  // the sum so far, carried by lane 0
+            }
             acc = pjoin<P>(acc, lbi_pass<P, M, false>(xp, yv, sg, sh, w, n, lane, rj));
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) acc = pjoin<P>(acc, __shfl_xor(acc, off));
             if (lane == t) s2_mine = acc;
         }
         const bool active = lane < cnt;
-        const float s2 = pjoin<P>(active ? a.S1[q * a.ldS + c_mine] : 0.f, s2_mine);
+        const float s2 = pjoin<P>(s1_mine, s2_mine);
         if (a.out_root && active) a.out_root[c_mine] = root_p<P>(s2);
         if (a.thr) {
             const bool keep = active && make_key(s2, c_mine) < a.thr[q];

@@ -248,6 +248,29 @@ def test_nn_search_pd_prefilter(L, ctx, mode, p, k, n, w):
     db.close()
 
 
+@pytest.mark.parametrize("n,w", [(128, 13), (256, 26), (300, 80), (512, 102), (2300, 600)])
+@pytest.mark.parametrize("p,k", [(1, 1), (2, 3), (INF, 1)])
+def test_nn_search_lbi_abandon(L, ctx, n, w, p, k):
+    """Early abandoning inside LB_Improved (register, wave-per-pair and generic kernels) changes
+    neither the answers nor any pruning count: a pair is abandoned only once its growing bound
+    has reached the threshold it would have reached anyway."""
+    _say(f"nn_search lbi_abandon n={n} w={w} p={p} k={k}")
+    X = walks(3000 if n < 1000 else 300, n, 36)
+    Ys = walks(9, n, 37)
+    db = L.Db(ctx, to_dev(X))
+    Yd = to_dev(Ys)
+    ri, rd, rst = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
+    L.lbimp_ctx_set_option(ctx, "lbi_abandon", 1)
+    try:
+        idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
+    finally:
+        L.lbimp_ctx_set_option(ctx, "lbi_abandon", 0)
+    assert torch.equal(idx, ri) and torch.equal(dist, rd)
+    assert np.array_equal(st[:, :5], rst[:, :5]) and np.array_equal(st[:, 6], rst[:, 6])
+    check_knn(X, Ys[:3], w, p, k, idx.cpu().numpy()[:3], dist.cpu().numpy()[:3], f"lbi_abandon n={n} w={w}")
+    db.close()
+
+
 # ------------------------------------------------------------------ nearest-neighbour search
 def oracle_knn(X, Ys, w, p, k):
     idx, dist = native.nn_bruteforce(X, Ys, R.effective_band(X.shape[1], w), p, k)
