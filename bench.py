@@ -136,17 +136,17 @@ def golden_errors(name, idx, dist, p):
                 rel_err_p99=float(np.percentile(rel, 99)))
 
 
-def stage_profile(L, ctx, db, Yd, w, p, mode, steps):
+def stage_profile(L, ctx, db, Yd, w, p, mode, steps, k=1):
     import torch
     L.lbimp_ctx_set_timing(ctx, True)
     acc = {}
     for _ in range(steps):
-        L.lbimp_nn_search(ctx, db, Yd, w, p, 1, mode, stats=False)
-        for k, v in L.lbimp_ctx_stage_times(ctx).items():
-            acc[k] = acc.get(k, 0.0) + v
+        L.lbimp_nn_search(ctx, db, Yd, w, p, k, mode, stats=False)
+        for name, v in L.lbimp_ctx_stage_times(ctx).items():
+            acc[name] = acc.get(name, 0.0) + v
     L.lbimp_ctx_set_timing(ctx, False)
     torch.cuda.synchronize()
-    return {k: v / steps for k, v in acc.items()}
+    return {name: v / steps for name, v in acc.items()}
 
 
 def big_database(L, ctx):
@@ -500,7 +500,8 @@ def main():
     ap.add_argument("--no-triangle", action="store_true", help="skip the App. B triangle-inequality workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
-    ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle", "pd", "abandon"),
+    ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle", "pd", "abandon",
+                                       "batch1m"),
                     help="run only the uneven-batch or the serving measurement and print its JSON (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -526,6 +527,21 @@ def main():
         return
     if args.only == "shapes":
         print(json.dumps(shape_bench(L, args.steps)), flush=True)
+        return
+    if args.only == "batch1m":
+        # one serving-sized batch: 410 random-walk queries over the 1,000,000 x 128 database,
+        # w = 13, p = 1, k = 10, two-pass search (the shape profiled for the LB_Improved and DTW
+        # counters of a serving batch)
+        ctx = L.Ctx(0)
+        big = big_database(L, ctx)
+        Yq = torch.from_numpy(gen.random_walk(410, 128, gen.rng(5, gen.ROLE_QUERY, 8)).astype(np.float32)).cuda()
+        for _ in range(args.warmup + args.steps):
+            L.lbimp_nn_search(ctx, big, Yq, 13, 1, 10, "improved", stats=False)
+        torch.cuda.synchronize()
+        st = stage_profile(L, ctx, big, Yq, 13, 1, "improved", 3, k=10)
+        print(json.dumps({"batch1m_stage_ms": st}), flush=True)
+        big.close()
+        ctx.close()
         return
     if args.only == "abandon":
         print(json.dumps(lbi_abandon_bench(L, args.steps)), flush=True)

@@ -162,14 +162,18 @@ struct DtwArgs {
 // Lower bound of a pair's DTW_p once rows 0..i are done: the minimum of row i plus the
 // LB_Keogh^p terms of the rows after i, which every remaining step of a path pays at least
 // (a cell (r, j) costs d(x_r, y_j)^p >= d(x_r, [L_r, U_r])^p).  The tail is S1 (the sweep's
-// sum over all rows) minus the rows already done.  Summation-order rounding of both sums and
-// of the DP itself is below (3n + 4) ulp of the final value (each term is at most the final
-// DTW, S1 included), so the sum is scaled down by (3n + 10) ulp: the bound never exceeds the
-// DTW computed in fp32, and abandoning on it changes no result.
+// sum over all rows) minus the rows already done.
+// Rounding (u = 2^-24, D the exact DTW; every quantity below is at most D because LB_Keogh and
+// any row minimum are):  the fp32 DTW is the rounded sum along some path of at most 2n - 1
+// cells, each term carrying up to two roundings for p = 2, so it is at least D (1 - (2n + 3) u);
+// the row minimum is such a partial sum, at most its exact value times (1 + (2n + 3) u); S1 and
+// the running sum "done" carry at most n u S1 each, and S1 - done and the final add one u more.
+// The computed bound is therefore at most D (1 + (4n + 8) u), and scaling it by
+// 1 - (6n + 16) u keeps it at or below the fp32 DTW: abandoning on it changes no result.
 __device__ __forceinline__ float cascade_bound(float rowmin, float s1, float done, float shrink) {
     return (rowmin + fmaxf(s1 - done, 0.f)) * shrink;
 }
-__host__ __device__ inline float cascade_shrink(int n) { return 1.f - (3.f * n + 10.f) * 5.9604645e-8f; }
+__host__ __device__ inline float cascade_shrink(int n) { return 1.f - (6.f * n + 16.f) * 5.9604645e-8f; }
 
 // LB_Keogh^p term of one element against the envelope [lo, hi].
 template <int P>
