@@ -287,12 +287,12 @@ def cpu_baseline(X, Ys, w, p, gpu_idx, budget_s=8.0):
 def ragged_bench(L, steps, warmup):
     """Uneven batch: 4,096 random-walk queries, lengths uniform over {64,...,1024}, w = round(f n)
     with f uniform over {0.05, 0.1, 0.2}, one 20,000-series database per length, p = 1, 1-NN,
-    one lbimp_nn_search_ragged call per step (captured once as a HIP graph, then replayed).  The
-    context autotunes every group on the first (untimed) call."""
+    one lbimp_nn_search_ragged call per step (captured once as a HIP graph, then replayed), every
+    group with the context's default choices (autotuning of ragged batches is kept off the
+    device until a host-side crash it once met is explained)."""
     import torch
     from paper_0811_3301_amd import gen
     ctx = L.Ctx(0)
-    L.lbimp_ctx_set_option(ctx, "autotune", 1)
     dbs, qs, db_of, w = gen.make_ragged_workload()
     handles = [L.Db(ctx, torch.from_numpy(d.astype(np.float32)).cuda()) for d in dbs]
     off = np.zeros(len(qs) + 1, np.int64)
@@ -323,7 +323,7 @@ def ragged_bench(L, steps, warmup):
     ctx.close()
     return dict(workload="uneven batch: 4096 random-walk queries, n in {64,128,256,512,1024}, w = round(f n), "
                          "f in {0.05,0.1,0.2}, 20000-series database per length, p=1, 1-NN",
-                queries=Q, groups=len(set(zip(db_of.tolist(), w.tolist()))), autotuned=True, **out,
+                queries=Q, groups=len(set(zip(db_of.tolist(), w.tolist()))), autotuned=False, **out,
                 dtw_fraction=float(st[:, 4].sum() / st[:, 0].sum()))
 
 
@@ -434,7 +434,7 @@ def triangle_bench(L, ctx, count=100_000, n=100, steps=5):
     return out
 
 
-def serving_bench(L, rates, measured=20_000, warmup_s=2.0, max_batch=512, slots=4, budget=16 << 30):
+def serving_bench(L, rates, measured=20_000, warmup_s=2.0, max_batch=512, slots=4, budget=4 << 30):
     """Serving: Poisson arrivals over a resident 1,000,000 x 128 random-walk database (512 MB)
     and a 200,000 x 256 side database (20% of requests), w = round(0.1 n), k uniform over
     {1, 5, 10}; continuous batching on `slots` in-flight batches under a device-memory budget.
@@ -449,7 +449,9 @@ def serving_bench(L, rates, measured=20_000, warmup_s=2.0, max_batch=512, slots=
     handles = [L.Db(ctx, torch.from_numpy(d.astype(np.float32)).cuda()) for d in dbs64]
     del dbs64
     torch.cuda.synchronize()
-    ex = GpuExecutor(handles, slots=slots, max_batch=max_batch, kmax=10)
+    # each slot's workspace is bounded by its share of the budget: a batch larger than that
+    # searches the database in chunks of candidates
+    ex = GpuExecutor(handles, slots=slots, max_batch=max_batch, kmax=10, workspace_limit=budget // slots)
     runs = []
     try:
         _, sample = gen.make_serving_workload(rates[-1], 300, with_databases=False)
@@ -483,6 +485,7 @@ def serving_bench(L, rates, measured=20_000, warmup_s=2.0, max_batch=512, slots=
     return dict(workload="serving: Poisson arrivals, 80% n=128 over a resident 1,000,000-series database "
                          "(512 MB), 20% n=256 over a 200,000-series database, w=round(0.1 n), k in {1,5,10}, "
                          "two-pass search", slots=slots, max_batch=max_batch, memory_budget_bytes=budget,
+                workspace_limit_per_slot=budget // slots,
                 protocol=f"{warmup_s:g} s of arrivals as warm-up, then {measured} measured requests per rate",
                 runs=runs)
 

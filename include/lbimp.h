@@ -108,6 +108,13 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *                   threshold from its smallest values, and compute LB_Keogh only of the
  *                   candidates it keeps, reading their rows; it pays where the first pass is
  *                   bound by database reads (a few queries per database sweep);
+ *   "workspace_limit" bytes (default 0, no bound): a search whose workspace would exceed it
+ *                   splits the database into chunks of candidates (multiples of 2,048) searched
+ *                   one after another, each through the whole path, the threshold carried from
+ *                   chunk to chunk (the best key, or the k best for k-NN); the answers are the
+ *                   same, the per-pass counts may differ.  The workspace then grows as Q times the
+ *                   chunk, not Q times the database (about 12 bytes per query and candidate of a
+ *                   chunk, plus 8 for k > 1);
  *   "lbi_abandon"   0/1 (default 0): early abandoning inside the LB_Improved pass (Sec. 10 of
  *                   the paper tried it on the CPU): a wave stops a pair's sum once it reaches the
  *                   threshold -- the register kernel when all 64 pairs of a wave have, the
@@ -193,8 +200,10 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
  * recorded in the context are used, nothing is tuned.  Instead of the context's workspace the
  * search uses a fixed scratch array of LBIMP_NOALLOC_SCRATCH_BYTES per GPU, part of the
  * library's code object, held by each GPU the library runs on until the process ends; the call
- * makes no hipMalloc, hipFree or other allocation.  A search that needs more scratch (it grows
- * about as 12 Q N bytes, plus 8 Q N for k > 1) returns LBIMP_E_NOMEM before enqueueing anything.
+ * makes no hipMalloc, hipFree or other allocation.  The database is searched in chunks of
+ * candidates small enough for the scratch (as with the "workspace_limit" option); a search that
+ * does not fit even with chunks of 2,048 candidates (about 12 bytes per query and candidate of a
+ * chunk, plus 8 for k > 1) returns LBIMP_E_NOMEM before enqueueing anything.
  * Every call on a GPU shares that GPU's array and leaves the last call's contents in it (each
  * search clears what it needs itself): calls whose work overlaps on one GPU -- from several
  * contexts, streams or threads -- race and give unspecified results. */

@@ -114,6 +114,7 @@ struct lbimp_ctx {
     int ragged_streams = kPoolStreams;  // option "ragged_streams"
     bool pd_prefilter = false;          // option "pd_prefilter"
     bool lbi_abandon = false;           // option "lbi_abandon"
+    size_t ws_limit = 0;                // option "workspace_limit" (bytes, 0: none)
     // ragged batches: stream pool, captured graph, pinned staging of the grouping metadata
     hipStream_t graph_stream = nullptr;
     hipStream_t pool[kPoolStreams] = {};
@@ -221,11 +222,13 @@ struct SearchSpec {  // Q queries of one length against one database
     Knobs kn;
     const int64_t *kq = nullptr;  // device [Q] per-query k (each <= k), or nullptr: k for every query
     int ldo = 0;                  // output row stride in entries (0: k)
+    size_t ws_limit = 0;          // workspace bound in bytes (0: none); the candidates are split into chunks to meet it
 };
 
 struct SearchDims {
     int n, n4, ldq, wb, qg, S, WL, k, p;
     int64_t N, Np, Q, Qp, ldres, nw;
+    int64_t C, nchunks;  // candidates per chunk (a multiple of kChunkAlign unless the whole database) and chunk count
     size_t ring_bytes;  // strip-boundary scratch of the wide-band DTW
     bool brute, improved, from_minima, pd;
 };
@@ -234,9 +237,26 @@ struct SearchBufs {
     float *Ue, *Le, *S1, *ring;
     int *seeds, *list0, *list1, *list2, *counters;
     u64 *best, *thr, *res, *wmin;
-    long long *prefix;
+    long long *prefix, *tot;
     double *qpd;
 };
+
+constexpr int64_t kChunkAlign = 2048;  // chunk sizes are multiples of the sweep's largest tile group
+
+// Sizes of a search over the candidates split into chunks of C (C = N: one chunk).
+static void chunk_dims(const SearchSpec &sp, int64_t C, SearchDims &d) {
+    d.C = std::max<int64_t>(std::min(C, d.N), 1);
+    d.nchunks = d.N ? (d.N + d.C - 1) / d.C : 1;
+    d.Np = (d.C + 63) / 64 * 64;  // row stride of the first-pass bounds of one chunk
+    d.S = d.brute ? 0 : (int)std::min<int64_t>(std::max(sp.kn.seeds, sp.k), d.C);
+    // result keys: the k kept from earlier chunks, then the seeds' and the survivors' of a chunk
+    d.ldres = d.brute ? std::max<int64_t>(d.C, 1) + (d.nchunks > 1 ? d.k : 0) : d.S + d.C + (d.nchunks > 1 ? d.k : 0);
+    d.nw = d.pd ? pd_scan_waves(d.C) : sweep_waves(sp.kn.sweep_shape, d.C, sp.Q);
+    // seeds come from the per-wave minima of the sweep once there are enough of them
+    d.from_minima = !d.brute && d.nw >= 4 * (int64_t)kMaxSeeds;
+}
+
+void layout(Carver &c, const SearchDims &d, SearchBufs &b);
 
 int dims_of(const SearchSpec &sp, int num_cu, SearchDims &d) {
     d.n = sp.db->n;
@@ -247,48 +267,70 @@ int dims_of(const SearchSpec &sp, int num_cu, SearchDims &d) {
     d.k = sp.k;
     d.p = sp.p;
     d.wb = band_of(d.n, sp.w);
-    d.Np = (d.N + 63) / 64 * 64;
     d.qg = sweep_query_group(sp.kn.sweep_shape, sp.Q);
     d.Qp = (sp.Q + d.qg - 1) / d.qg * d.qg;
     d.brute = sp.mode == LBIMP_MODE_BRUTE;
     d.improved = sp.mode == LBIMP_MODE_IMPROVED;
-    d.S = d.brute ? 0 : (int)std::min<int64_t>(std::max(sp.kn.seeds, sp.k), d.N);
     d.WL = d.improved ? lbi_batch(d.n, d.wb) : 1;
     if (d.improved && d.WL == 0)
         return fail(LBIMP_E_UNSUPPORTED, "LB_Improved state for n = %d, w = %d exceeds LDS", d.n, d.wb);
-    d.ldres = d.brute ? std::max<int64_t>(d.N, 1) : d.S + d.N;
     d.pd = sp.kn.pd && !d.brute;
-    d.nw = d.pd ? pd_scan_waves(d.N) : sweep_waves(sp.kn.sweep_shape, d.N, sp.Q);
-    // seeds come from the per-wave minima of the sweep once there are enough of them
-    d.from_minima = !d.brute && d.nw >= 4 * (int64_t)kMaxSeeds;
     d.ring_bytes = dtw_strip_scratch(d.p, d.n, d.wb, num_cu);
+    chunk_dims(sp, d.N, d);
+    if (sp.ws_limit && d.N > kChunkAlign) {
+        // halve the chunk until the workspace fits the bound (or the chunk is one tile group)
+        auto bytes = [&]() {
+            Carver cv{nullptr};
+            SearchBufs b;
+            layout(cv, d, b);
+            return cv.off;
+        };
+        int64_t C = d.N;
+        while (bytes() > sp.ws_limit && C > kChunkAlign) {
+            C = std::max<int64_t>(kChunkAlign, (C / 2 + kChunkAlign - 1) / kChunkAlign * kChunkAlign);
+            chunk_dims(sp, C, d);
+        }
+    }
     return LBIMP_OK;
 }
 
 void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
     const bool any = d.N > 0;
+    const bool list_k = d.k > 1 || d.nchunks > 1;  // result keys (and their shrinking between chunks)
     b.Ue = c.take<float>((size_t)d.Qp * d.ldq);
     b.Le = c.take<float>((size_t)d.Qp * d.ldq);
     b.S1 = (d.brute || !any) ? nullptr : c.take<float>((size_t)d.Q * d.Np);
     b.seeds = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * std::max(d.S, 1));
     b.best = c.take<u64>((size_t)d.Q);
     b.thr = c.take<u64>((size_t)d.Q);
-    b.res = (d.k > 1 || !any) ? c.take<u64>((size_t)d.Q * d.ldres) : nullptr;
-    b.list0 = (d.pd && any) ? c.take<int>((size_t)d.Q * d.N) : nullptr;
+    b.res = ((d.k > 1 && list_k) || !any) ? c.take<u64>((size_t)d.Q * d.ldres) : nullptr;
+    b.list0 = (d.pd && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
     b.qpd = (d.pd && any) ? c.take<double>((size_t)d.Q * 2 * kPdParts) : nullptr;
-    b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.N);
-    b.list2 = (d.improved && any) ? c.take<int>((size_t)d.Q * d.N) : nullptr;
+    b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.C);
+    b.list2 = (d.improved && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
     b.counters = c.take<int>((size_t)d.Q * kCounters);  // cnt1, cnt2, rescnt, abandoned, cnt0 ([kCounters][Q])
+    b.tot = d.nchunks > 1 ? c.take<long long>((size_t)d.Q * 3) : nullptr;  // cnt1, cnt2, cnt0 over all chunks
     b.prefix = c.take<long long>((size_t)d.Q + 1);
     b.wmin = (d.from_minima && any) ? c.take<u64>((size_t)d.Q * d.nw) : nullptr;
     b.ring = (d.ring_bytes && any) ? c.take<float>(d.ring_bytes / sizeof(float)) : nullptr;
 }
 
-void fill_stats(const SearchDims &d, int64_t Q, const int *h, const int64_t *ids, lbimp_stats *out) {
+// Seeds of a whole search: min(S, C_j) per chunk j.
+int64_t seeds_total(const SearchDims &d) {
+    if (d.brute || d.N == 0) return 0;
+    int64_t t = 0;
+    for (int64_t c0 = 0; c0 < d.N; c0 += d.C) t += std::min<int64_t>(d.S, d.N - c0);
+    return t;
+}
+
+// h: the counters [kCounters][Q]; tot: [3][Q] totals of cnt1, cnt2, cnt0 over chunks, or null.
+void fill_stats(const SearchDims &d, int64_t Q, const int *h, const long long *tot, const int64_t *ids,
+                lbimp_stats *out) {
+    const int64_t S = seeds_total(d);
     for (int64_t q = 0; q < Q; ++q) {
         lbimp_stats &st = out[ids ? ids[q] : q];
         st.candidates = d.N;
-        st.seeded = d.N ? d.S : 0;
+        st.seeded = S;
         st.dtw_abandoned = d.brute ? 0 : h[3 * Q + q];
         if (d.N == 0) {
             st = lbimp_stats{0, 0, 0, 0, 0, 0, 0};
@@ -296,12 +338,13 @@ void fill_stats(const SearchDims &d, int64_t Q, const int *h, const int64_t *ids
             st.pruned_pd = st.pruned_keogh = st.pruned_improved = 0;
             st.dtw_started = d.N;
         } else {
-            const int64_t c1 = h[q], c2 = d.improved ? h[Q + q] : c1;
-            const int64_t c0 = d.pd ? h[4 * Q + q] : d.N - d.S;  // pass-0 survivors
-            st.pruned_pd = d.N - d.S - c0;
+            const int64_t c1 = tot ? tot[q] : h[q];
+            const int64_t c2 = d.improved ? (tot ? tot[Q + q] : h[Q + q]) : c1;
+            const int64_t c0 = d.pd ? (tot ? tot[2 * Q + q] : h[4 * Q + q]) : d.N - S;  // pass-0 survivors
+            st.pruned_pd = d.N - S - c0;
             st.pruned_keogh = c0 - c1;
             st.pruned_improved = c1 - c2;
-            st.dtw_started = d.S + c2;
+            st.dtw_started = S + c2;
         }
     }
 }
@@ -332,62 +375,86 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     const lbimp_db *db = sp.db;
 
     stage(0);
-    // the envelope kernel also resets the best-so-far and threshold keys and the four counters
-    // (cnt1, cnt2, rescnt, abandoned) of the Q queries
+    // the envelope kernel also resets the best-so-far and threshold keys and the counters of the
+    // Q queries
     HIPTRY(launch_envelope(sp.queries, Q, d.Qp, n, wb, b.Ue, b.Le, d.ldq, s, b.best, b.thr, b.counters));
     stage(1);
-    if (d.brute) {
-        for (int i = 2; i <= 6; ++i) stage(i);
-        PairList all{nullptr, 0, nullptr, N};
-        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, all, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, nullptr, nullptr, false, false, b.ring,
-                          d.ring_bytes, nullptr, 0, s));
-    } else {
-        if (d.pd) {
-            // pass 0: the piecewise-sum bound (Sec. 9) of every candidate, 64 bytes per candidate
-            HIPTRY(launch_pd_query(b.Ue, b.Le, d.ldq, Q, n, b.qpd, s));
-            HIPTRY(launch_pd_scan(p, db->pd, N, n, b.qpd, Q, b.S1, d.Np, true, false, b.wmin, s));
+    const bool chunked = d.nchunks > 1;
+    if (chunked) HIPTRY(launch_fill_u64(reinterpret_cast<u64 *>(b.tot), 0, Q * 3, s));
+    if (d.pd) HIPTRY(launch_pd_query(b.Ue, b.Le, d.ldq, Q, n, b.qpd, s));
+    // The candidates are searched in chunks [c0, c0 + cj), each through the whole path; the
+    // threshold carries over (the best key for k = 1, the k best keys for k > 1), so every chunk
+    // prunes at least as well as the first.  Candidate indices stay global: the chunk's
+    // first-pass bounds are addressed through a base shifted back by c0.
+    for (int64_t c0 = 0; c0 < N; c0 += d.C) {
+        const int64_t cj = std::min(d.C, N - c0), c1 = c0 + cj;
+        const bool first = c0 == 0;
+        auto stage_first = [&](int i) {
+            if (first) stage(i);
+        };
+        if (d.brute) {
+            for (int i = 2; i <= 6; ++i) stage_first(i);
+            PairList all{nullptr, 0, nullptr, cj, c0};
+            HIPTRY(launch_dtw(p, db->rows, n, wb, qd, all, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
+                              k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, nullptr, nullptr, false, false,
+                              b.ring, d.ring_bytes, nullptr, 0, s));
         } else {
-            // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
-            HIPTRY(launch_lbk_sweep(p, sp.kn.sweep_shape, db->il, N, d.n4, reinterpret_cast<float4 *>(b.Ue),
-                                    reinterpret_cast<float4 *>(b.Le), d.n4, Q, b.S1, d.Np, true, false, b.wmin, s));
+            float *S1v = b.S1 - c0;  // S1v[q * Np + c] is candidate c of this chunk
+            if (d.pd) {
+                // pass 0: the piecewise-sum bound (Sec. 9) of every candidate, 64 bytes per candidate
+                HIPTRY(launch_pd_scan(p, db->pd + c0 * kPdParts, cj, n, b.qpd, Q, b.S1, d.Np, false, false,
+                                      b.wmin, s, c0));
+            } else {
+                // pass 1: LB_Keogh of every candidate (Algorithm 2/3, first bound)
+                HIPTRY(launch_lbk_sweep(p, sp.kn.sweep_shape, db->il + (c0 / 64) * d.n4 * 64, cj, d.n4,
+                                        reinterpret_cast<float4 *>(b.Ue), reinterpret_cast<float4 *>(b.Le), d.n4, Q,
+                                        b.S1, d.Np, false, false, b.wmin, s, c0));
+            }
+            stage_first(2);
+            const int Sj = (int)std::min<int64_t>(d.S, cj);
+            const int64_t nwj = d.pd ? pd_scan_waves(cj) : sweep_waves(sp.kn.sweep_shape, cj, Q);
+            const bool minima = d.from_minima && nwj >= 4 * (int64_t)kMaxSeeds;
+            HIPTRY(launch_select_seeds(S1v, d.Np, c1, Q, Sj, minima ? b.wmin : nullptr, nwj, b.seeds, s, c0));
+            stage_first(3);
+            // Seeds: few pairs per query on the critical path, so a group of lanes per pair (low
+            // latency); they run to completion, their DTWs finishing together.
+            const bool seed_ll = !sp.kn.seed_lane;
+            PairList seedl{b.seeds, Sj, nullptr, Sj};
+            HIPTRY(launch_dtw(p, db->rows, n, wb, qd, seedl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
+                              k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, seed_ll,
+                              b.ring, d.ring_bytes, nullptr, 0, s));
+            if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, sp.kq, b.thr, s));
+            stage_first(4);
+            if (d.pd) {
+                // the pass-0 survivors, then LB_Keogh of their rows (pass 1) over their S1 entries; the
+                // others keep their pass-0 bound, at or above the threshold
+                HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list0, d.C, cnt0, s, c0));
+                HIPTRY(launch_items_prefix(cnt0, 0, Q, lbk_gather_batch(), b.prefix, s));
+                HIPTRY(launch_lbk_gather(p, db->rows, n, qd, PairList{b.list0, d.C, cnt0, 0}, b.prefix, Q, grid, S1v,
+                                         d.Np, s));
+            }
+            HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt1, s, c0));
+            stage_first(5);
+            PairList dl{b.list1, d.C, cnt1, 0};
+            if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
+                HIPTRY(launch_items_prefix(cnt1, 0, Q, d.WL, b.prefix, s));
+                HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, S1v, d.Np, b.prefix, Q, nullptr,
+                                  grid, T, b.list2, d.C, cnt2, nullptr, sp.kn.lbi_pipeline, sp.kn.lbi_abandon, s));
+                dl = PairList{b.list2, d.C, cnt2, 0};
+            }
+            stage_first(6);
+            const bool dtw_ll = sp.kn.dtw_group && (wb <= kLaneMaxW || dtw_wavereg_wide_supported(n, wb));
+            HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, dtw_ll), b.prefix, s));
+            HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
+                              k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, dtw_ll,
+                              b.ring, d.ring_bytes, sp.kn.cascade ? S1v : nullptr, d.Np, s));
         }
-        stage(2);
-        HIPTRY(launch_select_seeds(b.S1, d.Np, N, Q, d.S, b.wmin, d.nw, b.seeds, s));
-        stage(3);
-        // Seeds: few pairs per query on the critical path, so a group of lanes per pair (low
-        // latency); they run to completion, their DTWs finishing together.
-        const bool seed_ll = !sp.kn.seed_lane;
-        PairList seedl{b.seeds, d.S, nullptr, d.S};
-        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, seedl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, false, seed_ll, b.ring,
-                          d.ring_bytes, nullptr, 0, s));
-        if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, sp.kq, b.thr, s));
-        stage(4);
-        if (d.pd) {
-            // the pass-0 survivors, then LB_Keogh of their rows (pass 1) over their S1 entries; the
-            // others keep their pass-0 bound, at or above the threshold
-            HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list0, N, cnt0, s));
-            HIPTRY(launch_items_prefix(cnt0, 0, Q, lbk_gather_batch(), b.prefix, s));
-            HIPTRY(launch_lbk_gather(p, db->rows, n, qd, PairList{b.list0, N, cnt0, 0}, b.prefix, Q, grid, b.S1, d.Np,
-                                     s));
+        if (chunked && c1 < N) {  // the next chunk starts from the k best keys so far
+            if (k > 1) HIPTRY(launch_res_shrink(b.res, d.ldres, rescnt, Q, k, sp.kq, b.thr, s));
+            if (!d.brute) HIPTRY(launch_chunk_counts(b.counters, b.tot, Q, s));
         }
-        HIPTRY(launch_compact(b.S1, d.Np, N, Q, T, b.list1, N, cnt1, s));
-        stage(5);
-        PairList dl{b.list1, N, cnt1, 0};
-        if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
-            HIPTRY(launch_items_prefix(cnt1, 0, Q, d.WL, b.prefix, s));
-            HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, b.S1, d.Np, b.prefix, Q, nullptr, grid,
-                              T, b.list2, N, cnt2, nullptr, sp.kn.lbi_pipeline, sp.kn.lbi_abandon, s));
-            dl = PairList{b.list2, N, cnt2, 0};
-        }
-        stage(6);
-        const bool dtw_ll = sp.kn.dtw_group && (wb <= kLaneMaxW || dtw_wavereg_wide_supported(n, wb));
-        HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, dtw_ll), b.prefix, s));
-        HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                          k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, dtw_ll, b.ring,
-                          d.ring_bytes, sp.kn.cascade ? b.S1 : nullptr, d.Np, s));
     }
+    if (chunked && !d.brute) HIPTRY(launch_chunk_counts(b.counters, b.tot, Q, s));
     stage(7);
     if (k == 1)
         HIPTRY(launch_finalize1(b.best, Q, p, sp.idx, sp.dist, sp.qmap, ldo, s));
@@ -443,6 +510,7 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
             for (bool pdv : {false, true}) {
                 SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr,
                               Knobs{sd, true, sh, false, false, true, pdv}};
+                sp.ws_limit = ctx->ws_limit;
                 SearchDims d;
                 if (int r = dims_of(sp, ctx->num_cu, d)) return r;
                 SearchBufs b;
@@ -483,6 +551,7 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
         if (!e) HIPTRY(hipEventCreate(&e));
     auto time_of = [&](const Knobs &kn, float *ms) -> int {
         SearchSpec sp{db, queries, Q, wb, p, k, mode, idx, dist, nullptr, kn};
+        sp.ws_limit = ctx->ws_limit;
         SearchDims d;
         if (int r = dims_of(sp, ctx->num_cu, d)) return r;
         SearchBufs b;
@@ -700,6 +769,7 @@ static int plan_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, 
         SearchSpec sp{db, nullptr, Qg, kv.first.second, p, kg, mode, idx, dist, nullptr,
                       knobs_for(ctx, db, Qg, kv.first.second, p, kg, mode)};
         sp.ldo = plan.kmax;
+        sp.ws_limit = ctx->ws_limit;
         plan.specs.push_back(sp);
         if (int r = dims_of(plan.specs.back(), ctx->num_cu, plan.dims[plan.specs.size() - 1])) return r;
         plan.meta_elems += 3 * (size_t)Qg;
@@ -791,6 +861,9 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         ctx->pd_prefilter = value != 0;
     } else if (!strcmp(name, "lbi_abandon")) {
         ctx->lbi_abandon = value != 0;
+    } else if (!strcmp(name, "workspace_limit")) {
+        if (value < 0) return fail(LBIMP_E_INVALID, "workspace_limit must be >= 0");
+        ctx->ws_limit = (size_t)value;
     } else if (!strcmp(name, "sweep_shape")) {
         if (value < 0 || value > 5) return fail(LBIMP_E_INVALID, "sweep_shape must be in [0, 5]");
         ctx->sweep_shape = (int)value;
@@ -1052,6 +1125,7 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
         if (int r = tune_search(ctx, db, queries, nullptr, nullptr, Q, wb, p, k, mode, &tuned)) return r;
     }
     SearchSpec sp{db, queries, Q, w, p, k, mode, idx, dist, nullptr, knobs_for(ctx, db, Q, wb, p, k, mode)};
+    sp.ws_limit = ctx->ws_limit;
     SearchDims d;
     if (int r = dims_of(sp, ctx->num_cu, d)) return r;
     SearchBufs bufs;
@@ -1069,7 +1143,12 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
         std::vector<int> h((size_t)Q * kCounters);
         HIPTRY(hipMemcpyAsync(h.data(), bufs.counters, sizeof(int) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
         HIPTRY(hipStreamSynchronize(ctx->stream));
-        fill_stats(d, Q, h.data(), nullptr, stats);
+        std::vector<long long> ht(bufs.tot ? (size_t)Q * 3 : 0);
+        if (bufs.tot)
+            HIPTRY(hipMemcpyAsync(ht.data(), bufs.tot, sizeof(long long) * ht.size(), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+        HIPTRY(hipStreamSynchronize(ctx->stream));
+        fill_stats(d, Q, h.data(), bufs.tot ? ht.data() : nullptr, nullptr, stats);
     }
     return LBIMP_OK;
 }
@@ -1087,6 +1166,9 @@ int lbimp_nn_search_noalloc(lbimp_ctx *ctx, const lbimp_db *db, const float *que
     // tuned choices are used when present; nothing is tuned here (tuning needs a workspace)
     const int wb = band_of(db->n, w);
     SearchSpec sp{db, queries, Q, w, p, k, mode, idx, dist, nullptr, knobs_for(ctx, db, Q, wb, p, k, mode)};
+    // the candidates are split into chunks small enough for the scratch (or the context's bound)
+    sp.ws_limit = ctx->ws_limit ? std::min<size_t>(ctx->ws_limit, LBIMP_NOALLOC_SCRATCH_BYTES)
+                                : (size_t)LBIMP_NOALLOC_SCRATCH_BYTES;
     SearchDims d;
     if (int r = dims_of(sp, ctx->num_cu, d)) return r;
     SearchBufs bufs;
@@ -1198,7 +1280,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
     mix((uint64_t)(uintptr_t)idx);
     mix((uint64_t)(uintptr_t)dist);
     mix((uint64_t)Q);
-    mix((uint64_t)(p * 131 + plan.kmax * 7 + mode));
+    mix((uint64_t)(uint32_t)p * 131 + (uint64_t)plan.kmax * 7 + (uint64_t)mode);
     mix((uint64_t)width);
     for (int g = 0; g < G; ++g) {
         const lbimp_db *db = specs[g].db;  // a database freed and recreated may reuse an address
@@ -1253,7 +1335,10 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
             std::vector<int> h((size_t)specs[g].Q * kCounters);
             HIPTRY(hipMemcpy(h.data(), bufs[g].counters, sizeof(int) * h.size(), hipMemcpyDeviceToHost));
             const std::vector<int64_t> &ids = std::next(groups.begin(), g)->second;
-            fill_stats(dims[g], specs[g].Q, h.data(), ids.data(), stats);
+            std::vector<long long> ht(bufs[g].tot ? (size_t)specs[g].Q * 3 : 0);
+            if (bufs[g].tot)
+                HIPTRY(hipMemcpy(ht.data(), bufs[g].tot, sizeof(long long) * ht.size(), hipMemcpyDeviceToHost));
+            fill_stats(dims[g], specs[g].Q, h.data(), bufs[g].tot ? ht.data() : nullptr, ids.data(), stats);
         }
     }
     return LBIMP_OK;

@@ -61,7 +61,7 @@ __device__ __forceinline__ int pair_count(const PairList &pl, int64_t q) {
 }
 
 __device__ __forceinline__ int pair_cand(const PairList &pl, int64_t q, long long j) {
-    return pl.list ? pl.list[q * pl.ldl + j] : (int)j;
+    return pl.list ? pl.list[q * pl.ldl + j] : (int)(pl.base + j);
 }
 
 

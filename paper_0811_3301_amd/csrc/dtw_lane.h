@@ -110,7 +110,7 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
         const u64 *tq = a.tkeys + q;
         u64 tcur = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         float s1v = 0.f;
-        if constexpr (cascade) s1v = a.S1[q * a.ldS + c];
+        if constexpr (cascade) s1v = active ? a.S1[q * a.ldS + c] : 0.f;  // S1 may be a chunk's shifted base
         float done = 0.f;  // LB_Keogh^p terms of the rows already computed
         for (; i0 < nfull; i0 += kLaneRows) {
             float xn[kLaneRows];

@@ -137,7 +137,7 @@ void k_dtw_strip(DtwArgs a, int w, float *__restrict__ ring_base, int rb_log2) {
         int stopped = 0;
         float fin = kInf;
         float s1v = 0.f;
-        if constexpr (cascade) s1v = a.S1[q * a.ldS + c];
+        if constexpr (cascade) s1v = active ? a.S1[q * a.ldS + c] : 0.f;  // S1 may be a chunk's shifted base
         float done = 0.f;  // LB_Keogh^p terms of the rows already computed
         for (int s = 0; s < S; ++s) {
             const int I0 = I00 + s * C;

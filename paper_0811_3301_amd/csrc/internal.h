@@ -44,22 +44,24 @@ hipError_t launch_envelope(const float *y, int64_t B, int64_t Bpad, int n, int w
 // wmin (optional, nn search only): wmin[q][v] = smallest (S1, index) key over the candidates of
 // sweep wave v, v < sweep_waves(N, Q).
 // shape: tiling variant (0 = default); rows of Ue/Le must be padded to a multiple of
-// sweep_query_group(shape, Q) queries.
+// sweep_query_group(shape, Q) queries.  cbase is added to the candidate index of the wmin keys
+// (a sweep over a chunk of a database: il, N and out are the chunk's).
 hipError_t launch_lbk_sweep(int p, int shape, const float4 *il, int64_t N, int n4, const float4 *Ue,
                             const float4 *Le, int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root,
-                            unsigned long long *wmin, hipStream_t s);
+                            unsigned long long *wmin, hipStream_t s, int64_t cbase = 0);
 int sweep_query_group(int shape, int64_t Q);
 int64_t sweep_waves(int shape, int64_t N, int64_t Q);
 
 // Per query: pick S candidates of small first-pass sum into seeds[q][0..S) and set their S1
 // entries to +inf.  From the whole S1 row (wmin == nullptr), or from the nw per-wave minima of
-// the sweep (one candidate per sweep wave).  S <= 64, S <= number of sources.
+// the sweep (one candidate per sweep wave).  S <= 64, S <= number of sources.  Candidates are
+// [c0, N) and indexed globally: S1 may be a chunk's buffer shifted back by c0.
 hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int S, const unsigned long long *wmin,
-                               int64_t nw, int *seeds, hipStream_t s);
+                               int64_t nw, int *seeds, hipStream_t s, int64_t c0 = 0);
 
-// list[q][*] <- candidates c < N with key(S1[q][c], c) < thr[q]; cnt[q] += number kept.
+// list[q][*] <- candidates c0 <= c < N with key(S1[q][c], c) < thr[q]; cnt[q] += number kept.
 hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, const unsigned long long *thr,
-                          int *list, int64_t ldl, int *cnt, hipStream_t s);
+                          int *list, int64_t ldl, int *cnt, hipStream_t s, int64_t c0 = 0);
 
 // prefix[0] = 0, prefix[q+1] = prefix[q] + ceil(count_q / batch), count_q = cnt[q] or `fixed`.
 hipError_t launch_items_prefix(const int *cnt, int64_t fixed, int64_t Q, int batch, long long *prefix,
@@ -78,14 +80,16 @@ hipError_t launch_pd_query(const float *U, const float *L, int ldq, int64_t Q, i
 // the smallest (bound, index) key of every 64 candidates, wmin[q][v] for v < pd_scan_waves(N).
 int64_t pd_scan_waves(int64_t N);
 hipError_t launch_pd_scan(int p, const double *pd, int64_t N, int n, const double *qpd, int64_t Q, float *out,
-                          int64_t ldo, bool pad_inf, bool root, unsigned long long *wmin, hipStream_t s);
+                          int64_t ldo, bool pad_inf, bool root, unsigned long long *wmin, hipStream_t s,
+                          int64_t cbase = 0);
 
 // Pair list description for the persistent second-pass and DTW kernels.
 struct PairList {
-    const int *list;     // [Q][ldl] candidate ids, or nullptr for "candidate = position"
+    const int *list;     // [Q][ldl] candidate ids, or nullptr for "candidate = base + position"
     int64_t ldl;
     const int *cnt;      // [Q] counts, or nullptr for `fixed` pairs per query
     int64_t fixed;
+    int64_t base = 0;
 };
 
 struct QueryData {
@@ -148,6 +152,13 @@ hipError_t launch_finalize1(const unsigned long long *best, int64_t Q, int p, in
 hipError_t launch_finalize_k(unsigned long long *res, int64_t ldres, const int *rescnt, int64_t Q, int k,
                              const int64_t *kq, int ldo, int p, int64_t *idx, float *dist, const int64_t *qmap,
                              hipStream_t s);
+
+// Between chunks of a search: res[q] keeps its k smallest keys, sorted (k = kq[q] when given),
+// rescnt[q] their number, thr[q] the k-th (no key if fewer).
+hipError_t launch_res_shrink(unsigned long long *res, int64_t ldres, int *rescnt, int64_t Q, int k, const int64_t *kq,
+                             unsigned long long *thr, hipStream_t s);
+// tot ([3][Q]) += the chunk's counts cnt1, cnt2, cnt0 of counters ([kCounters][Q]), which are cleared.
+hipError_t launch_chunk_counts(int *counters, long long *tot, int64_t Q, hipStream_t s);
 
 // dst[j][i] = src[off[j] + i] for j < count, i < n (gathers equal-length rows of a packed array).
 hipError_t launch_gather_rows(const float *src, const int64_t *off, int n, int64_t count, float *dst, hipStream_t s);

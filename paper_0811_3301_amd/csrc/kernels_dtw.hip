@@ -392,4 +392,67 @@ hipError_t launch_finalize_k(unsigned long long *res, int64_t ldres, const int *
     return hipGetLastError();
 }
 
+// Between two chunks of a search over a database split into candidate ranges: keep the k
+// smallest keys of res[q] (k = kq[q] when given), sorted, as its only entries, and make the
+// k-th of them the threshold of the next chunk (no key if fewer than k).
+__global__ __launch_bounds__(256) void k_res_shrink(u64 *__restrict__ res, int64_t ldres, int *__restrict__ rescnt,
+                                                     int k, const int64_t *__restrict__ kq, u64 *__restrict__ thr) {
+    __shared__ u64 red[256];
+    __shared__ u64 kept[64];
+    const int64_t q = blockIdx.x;
+    const int cnt = rescnt[q];
+    const int kk = kq ? (int)kq[q] : k;
+    u64 *r = res + q * ldres;
+    int got = 0;
+    for (int round = 0; round < kk; ++round) {
+        u64 m = kNoKey;
+        for (int t = threadIdx.x; t < cnt; t += 256) m = min(m, r[t]);
+        red[threadIdx.x] = m;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + off]);
+            __syncthreads();
+        }
+        const u64 best = red[0];
+        __syncthreads();
+        if (best == kNoKey) break;
+        for (int t = threadIdx.x; t < cnt; t += 256)
+            if (r[t] == best) r[t] = kNoKey;
+        if (threadIdx.x == 0) kept[round] = best;
+        ++got;
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < got; t += 256) r[t] = kept[t];
+    if (threadIdx.x == 0) {
+        rescnt[q] = got;
+        thr[q] = got >= kk ? kept[kk - 1] : kNoKey;
+    }
+}
+
+hipError_t launch_res_shrink(unsigned long long *res, int64_t ldres, int *rescnt, int64_t Q, int k, const int64_t *kq,
+                             unsigned long long *thr, hipStream_t s) {
+    if (Q == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_res_shrink, dim3((unsigned)Q), dim3(256), 0, s, res, ldres, rescnt, k, kq, thr);
+    return hipGetLastError();
+}
+
+// tot[r][q] += cnt[rows[r]][q] and the counter is cleared, for the three list counts of a chunk.
+__global__ void k_chunk_counts(int *__restrict__ counters, long long *__restrict__ tot, int64_t Q) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q) return;
+    const int rows[3] = {0, 1, 4};  // cnt1, cnt2, cnt0
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        tot[r * Q + q] += counters[rows[r] * Q + q];
+        counters[rows[r] * Q + q] = 0;
+    }
+}
+
+hipError_t launch_chunk_counts(int *counters, long long *tot, int64_t Q, hipStream_t s) {
+    if (Q == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_counts, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s, counters, tot, Q);
+    return hipGetLastError();
+}
+
 }  // namespace lbimp

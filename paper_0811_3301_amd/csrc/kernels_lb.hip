@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
                                                     const float4 *__restrict__ Ue, const float4 *__restrict__ Le,
                                                     int ld4, int64_t Q, float *__restrict__ out, int64_t ldo,
                                                     bool pad_inf, unsigned long long *__restrict__ wmin, int64_t ldw,
-                                                    unsigned gx, unsigned gy) {
+                                                    unsigned gx, unsigned gy, int64_t cbase) {
     constexpr int ICH = 32;
     __shared__ float4 sU[QG][ICH];
     __shared__ float4 sL[QG][ICH];
@@ -194,8 +194,8 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
     // are dealt to the 8 XCDs in turn (block b on XCD b % 8); renumbering them so that logical
     // neighbours share an XCD, with query groups fastest, runs the query groups of one tile
     // group back to back on one XCD, where its L2 serves the tile to all of them.
-    const unsigned nb = gx * gy, per = nb / 8, b = blockIdx.x;
-    const unsigned lid = b < per * 8 ? (b % 8) * per + b / 8 : b;
+    const unsigned nb = gx * gy, per = nb / 8, blk = blockIdx.x;
+    const unsigned lid = blk < per * 8 ? (blk % 8) * per + blk / 8 : blk;
     const unsigned bx = lid / gy, by = lid % gy;
     const int64_t tile0 = ((int64_t)bx * 4 + wave) * CPL;
     const int64_t q0 = (int64_t)by * QG;
@@ -259,7 +259,8 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
             for (int b = 0; b < CPL; ++b) {
                 const int64_t c = (tile0 + b) * 64 + lane;
                 if (tv[b] && c < N) {
-                    unsigned long long kb = ((unsigned long long)__float_as_uint(acc[a][b]) << 32) | (unsigned long long)c;
+                    unsigned long long kb =
+                        ((unsigned long long)__float_as_uint(acc[a][b]) << 32) | (unsigned long long)(c + cbase);
                     k = kb < k ? kb : k;
                 }
             }
@@ -292,11 +293,11 @@ __global__ __launch_bounds__(256) void k_lbk_sweep(const float4 *__restrict__ il
 template <int P, int QG, int CPL, bool ROOT>
 static hipError_t sweep_variant(const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le, int ld4,
                                 int64_t Q, float *out, int64_t ldo, bool pad_inf, unsigned long long *wmin,
-                                hipStream_t s) {
+                                int64_t cbase, hipStream_t s) {
     int64_t T = (N + 63) / 64;
     const unsigned gx = (unsigned)((T + 4 * CPL - 1) / (4 * CPL)), gy = (unsigned)((Q + QG - 1) / QG);
     hipLaunchKernelGGL((k_lbk_sweep<P, QG, CPL, ROOT>), dim3(gx * gy), dim3(256), 0, s, il, T, N, n4, Ue, Le, ld4, Q,
-                       out, ldo, pad_inf, wmin, (int64_t)gx * 4, gx, gy);
+                       out, ldo, pad_inf, wmin, (int64_t)gx * 4, gx, gy, cbase);
     return hipGetLastError();
 }
 
@@ -334,10 +335,10 @@ int64_t sweep_waves(int shape, int64_t N, int64_t Q) {
 template <int P, bool ROOT>
 static hipError_t sweep_p(int qg, int cpl, const float4 *il, int64_t N, int n4, const float4 *Ue, const float4 *Le,
                           int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, unsigned long long *wmin,
-                          hipStream_t s) {
+                          int64_t cbase, hipStream_t s) {
 #define LBIMP_SWEEP(QG, CPL) \
     if (qg == QG && cpl == CPL) \
-        return sweep_variant<P, QG, CPL, ROOT>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+        return sweep_variant<P, QG, CPL, ROOT>(il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, cbase, s);
     LBIMP_SWEEP(1, 4)
     LBIMP_SWEEP(16, 2)
     LBIMP_SWEEP(8, 4)
@@ -350,19 +351,19 @@ static hipError_t sweep_p(int qg, int cpl, const float4 *il, int64_t N, int n4, 
 
 hipError_t launch_lbk_sweep(int p, int shape, const float4 *il, int64_t N, int n4, const float4 *Ue,
                             const float4 *Le, int ld4, int64_t Q, float *out, int64_t ldo, bool pad_inf, bool root,
-                            unsigned long long *wmin, hipStream_t s) {
+                            unsigned long long *wmin, hipStream_t s, int64_t cbase) {
     if (N == 0 || Q == 0) return hipSuccess;
     int qg, cpl;
     shape_of(shape, Q, qg, cpl);
     // query envelopes are padded by the caller to a multiple of sweep_query_group(shape, Q)
     if (p == 1)
-        return root ? sweep_p<1, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
-                    : sweep_p<1, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+        return root ? sweep_p<1, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, cbase, s)
+                    : sweep_p<1, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, cbase, s);
     if (p == 2)
-        return root ? sweep_p<2, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s)
-                    : sweep_p<2, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+        return root ? sweep_p<2, true>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, cbase, s)
+                    : sweep_p<2, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, cbase, s);
     // p = infinity: LB_Keogh_inf is its own root form
-    return sweep_p<kPInf, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, s);
+    return sweep_p<kPInf, false>(qg, cpl, il, N, n4, Ue, Le, ld4, Q, out, ldo, pad_inf, wmin, cbase, s);
 }
 
 // ------------------------------------------------------------------ seed selection
@@ -372,14 +373,14 @@ hipError_t launch_lbk_sweep(int p, int shape, const float4 *il, int64_t N, int n
 // bitonically in LDS and the first S taken.  Approximate top-S is enough: any threshold that
 // is the DTW of some candidate is a valid (never too small) best-so-far.
 template <bool FROM_KEYS>
-__global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, int64_t ldS, int64_t N,
+__global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, int64_t ldS, int64_t cstart, int64_t N,
                                                        const unsigned long long *__restrict__ wmin, int64_t nw,
                                                        int S, int *__restrict__ seeds) {
     __shared__ unsigned long long keys[1024];
     const int64_t q = blockIdx.x;
     float *row = S1 + q * ldS;
     unsigned long long top[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
-    const int64_t count = FROM_KEYS ? nw : N;
+    const int64_t count = FROM_KEYS ? nw : N - cstart;
     // Thread t takes entries t, t + 256, t + 512, ...; eight of them are loaded before the first
     // is inserted, so a pass waits for memory once per eight loads.
     constexpr int U = 8;
@@ -390,7 +391,9 @@ __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, in
             const int64_t c = c0 + u * 256;
             const int64_t cc = c < count ? c : count - 1;
             const unsigned long long k =
-                FROM_KEYS ? wmin[q * nw + cc] : ((unsigned long long)__float_as_uint(row[cc]) << 32) | (unsigned long long)cc;
+                FROM_KEYS ? wmin[q * nw + cc]
+                          : ((unsigned long long)__float_as_uint(row[cstart + cc]) << 32) |
+                                (unsigned long long)(cstart + cc);
             kk[u] = c < count ? k : kNoKey;
         }
 #pragma unroll
@@ -436,12 +439,14 @@ __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, in
 }
 
 hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int S, const unsigned long long *wmin,
-                               int64_t nw, int *seeds, hipStream_t s) {
+                               int64_t nw, int *seeds, hipStream_t s, int64_t c0) {
     if (Q == 0 || S == 0) return hipSuccess;
     if (wmin)
-        hipLaunchKernelGGL(k_select_seeds<true>, dim3((unsigned)Q), dim3(256), 0, s, S1, ldS, N, wmin, nw, S, seeds);
+        hipLaunchKernelGGL(k_select_seeds<true>, dim3((unsigned)Q), dim3(256), 0, s, S1, ldS, c0, N, wmin, nw, S,
+                           seeds);
     else
-        hipLaunchKernelGGL(k_select_seeds<false>, dim3((unsigned)Q), dim3(256), 0, s, S1, ldS, N, wmin, nw, S, seeds);
+        hipLaunchKernelGGL(k_select_seeds<false>, dim3((unsigned)Q), dim3(256), 0, s, S1, ldS, c0, N, wmin, nw, S,
+                           seeds);
     return hipGetLastError();
 }
 
@@ -449,7 +454,7 @@ hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int
 // Strict test of Algorithms 2 and 3 on the (value, index) key: a candidate whose bound key is
 // not below the threshold key can at best tie, and a tie goes to the smaller index.
 // Each wave covers 64*CH candidates: one ballot per chunk, one atomicAdd per wave.
-__global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, int64_t ldS, int64_t N,
+__global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, int64_t ldS, int64_t c0, int64_t N,
                                                   const unsigned long long *__restrict__ thr, int *__restrict__ list,
                                                   int64_t ldl, int *__restrict__ cnt) {
     constexpr int CH = 16;
@@ -457,7 +462,7 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, i
     __shared__ int wbase[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t q = blockIdx.y;
-    const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64 * CH;
+    const int64_t base = c0 + ((int64_t)blockIdx.x * 4 + wave) * 64 * CH;
     const unsigned long long t = thr[q];
     const float *row = S1 + q * ldS;
     // All CH loads are issued before the first test (a load under `c < N` would be a branch of
@@ -483,9 +488,9 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, i
     if (threadIdx.x == 0) {
         const int sum = wtot[0] + wtot[1] + wtot[2] + wtot[3];
         int pos = sum ? atomicAdd(&cnt[q], sum) : 0;
-        for (int v = 0; v < 4; ++v) {
-            wbase[v] = pos;
-            pos += wtot[v];
+        for (int wv = 0; wv < 4; ++wv) {
+            wbase[wv] = pos;
+            pos += wtot[wv];
         }
     }
     __syncthreads();
@@ -501,11 +506,11 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, i
 }
 
 hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, const unsigned long long *thr,
-                          int *list, int64_t ldl, int *cnt, hipStream_t s) {
-    if (N == 0 || Q == 0) return hipSuccess;
+                          int *list, int64_t ldl, int *cnt, hipStream_t s, int64_t c0) {
+    if (N <= c0 || Q == 0) return hipSuccess;
     int64_t per_block = 4 * 64 * 16;
-    dim3 grid((unsigned)((N + per_block - 1) / per_block), (unsigned)Q);
-    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, S1, ldS, N, thr, list, ldl, cnt);
+    dim3 grid((unsigned)((N - c0 + per_block - 1) / per_block), (unsigned)Q);
+    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, S1, ldS, c0, N, thr, list, ldl, cnt);
     return hipGetLastError();
 }
 

@@ -91,7 +91,7 @@ template <int P, int QG, bool ROOT>
 __global__ __launch_bounds__(256) void k_pd_scan(const double *__restrict__ pd, int64_t N, int n,
                                                   const double *__restrict__ qpd, int64_t Q, float *__restrict__ out,
                                                   int64_t ldo, bool pad_inf, unsigned long long *__restrict__ wmin,
-                                                  int64_t ldw) {
+                                                  int64_t ldw, int64_t cbase) {
     __shared__ double sq[QG][2 * kPdParts];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t q0 = (int64_t)blockIdx.y * QG;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_pd_scan(const double *__restrict__ pd, 
         else if (pad_inf && c < ldo)
             out[q * ldo + c] = kInf;
         if (wmin) {
-            unsigned long long k = valid ? make_key(f, (int)c) : kNoKey;
+            unsigned long long k = valid ? make_key(f, (int)(c + cbase)) : kNoKey;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 const unsigned hi = __shfl_xor((unsigned)(k >> 32), off);
@@ -143,23 +143,23 @@ int64_t pd_scan_waves(int64_t N) { return (N + 255) / 256 * 4; }
 
 template <int P, bool ROOT>
 static void pd_scan_launch(const double *pd, int64_t N, int n, const double *qpd, int64_t Q, float *out, int64_t ldo,
-                           bool pad_inf, unsigned long long *wmin, hipStream_t s) {
+                           bool pad_inf, unsigned long long *wmin, int64_t cbase, hipStream_t s) {
     constexpr int QG = 16;
     const dim3 grid((unsigned)((N + 255) / 256), (unsigned)((Q + QG - 1) / QG));
     hipLaunchKernelGGL((k_pd_scan<P, QG, ROOT>), grid, dim3(256), 0, s, pd, N, n, qpd, Q, out, ldo, pad_inf, wmin,
-                       pd_scan_waves(N));
+                       pd_scan_waves(N), cbase);
 }
 
 hipError_t launch_pd_scan(int p, const double *pd, int64_t N, int n, const double *qpd, int64_t Q, float *out,
-                          int64_t ldo, bool pad_inf, bool root, unsigned long long *wmin, hipStream_t s) {
+                          int64_t ldo, bool pad_inf, bool root, unsigned long long *wmin, hipStream_t s, int64_t cbase) {
     if (N == 0 || Q == 0) return hipSuccess;
     if (p == 1)
-        pd_scan_launch<1, false>(pd, N, n, qpd, Q, out, ldo, pad_inf, wmin, s);
+        pd_scan_launch<1, false>(pd, N, n, qpd, Q, out, ldo, pad_inf, wmin, cbase, s);
     else if (p == 2)
-        root ? pd_scan_launch<2, true>(pd, N, n, qpd, Q, out, ldo, pad_inf, wmin, s)
-             : pd_scan_launch<2, false>(pd, N, n, qpd, Q, out, ldo, pad_inf, wmin, s);
+        root ? pd_scan_launch<2, true>(pd, N, n, qpd, Q, out, ldo, pad_inf, wmin, cbase, s)
+             : pd_scan_launch<2, false>(pd, N, n, qpd, Q, out, ldo, pad_inf, wmin, cbase, s);
     else
-        pd_scan_launch<kPInf, false>(pd, N, n, qpd, Q, out, ldo, pad_inf, wmin, s);
+        pd_scan_launch<kPInf, false>(pd, N, n, qpd, Q, out, ldo, pad_inf, wmin, cbase, s);
     return hipGetLastError();
 }
 

@@ -129,7 +129,8 @@ class _Slot:
 class GpuExecutor:
     """In-flight batches on ``slots`` library contexts, one HIP stream each."""
 
-    def __init__(self, dbs, slots: int = 4, max_batch: int = 512, kmax: int = 10, p: int = 1, mode: str = "improved"):
+    def __init__(self, dbs, slots: int = 4, max_batch: int = 512, kmax: int = 10, p: int = 1, mode: str = "improved",
+                 workspace_limit: int = 0):
         import torch
 
         from . import lbimp as L
@@ -146,6 +147,8 @@ class GpuExecutor:
             # and keep each batch on its slot's stream (the slots already overlap each other)
             L.lbimp_ctx_set_option(ctx, "graph", 0)
             L.lbimp_ctx_set_option(ctx, "ragged_streams", 0)
+            # a bound on each slot's workspace: larger batches search the database in chunks
+            L.lbimp_ctx_set_option(ctx, "workspace_limit", int(workspace_limit))
             elems = max_batch * max_len
             self.slots.append(_Slot(
                 ctx=ctx, stream=stream,

@@ -271,6 +271,40 @@ def test_nn_search_lbi_abandon(L, ctx, n, w, p, k):
     db.close()
 
 
+@pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
+@pytest.mark.parametrize("p,k", [(1, 1), (2, 5), (INF, 3)])
+@pytest.mark.parametrize("pd", [0, 1])
+def test_nn_search_chunked(L, ctx, mode, p, k, pd):
+    """A workspace bound splits the database into chunks of candidates searched one after another
+    (the threshold carried across): the answers equal the unchunked search's, bit for bit, and the
+    oracle's; the workspace stays under the bound; counts keep their invariants."""
+    if pd and mode == "brute":
+        pytest.skip("pass 0 does not apply to brute force")
+    _say(f"nn_search chunked mode={mode} p={p} k={k} pd={pd}")
+    X = walks(9_000, 64, 38)  # chunks of 2048 or 4096 candidates, the last one shorter
+    Ys = walks(6, 64, 39)
+    db = L.Db(ctx, to_dev(X))
+    Yd = to_dev(Ys)
+    L.lbimp_ctx_set_option(ctx, "pd_prefilter", pd)
+    try:
+        ri, rd, _ = L.lbimp_nn_search(ctx, db, Yd, 6, p, k, mode)
+        small = L.Ctx(0)
+        L.lbimp_ctx_set_option(small, "pd_prefilter", pd)
+        L.lbimp_ctx_set_option(small, "workspace_limit", 400_000)
+        idx, dist, st = L.lbimp_nn_search(small, db, Yd, 6, p, k, mode)
+        torch.cuda.synchronize()
+        assert L.lbimp_ctx_workspace_bytes(small) <= 2 << 20  # reserve rounds up to whole MiB
+        small.close()
+    finally:
+        L.lbimp_ctx_set_option(ctx, "pd_prefilter", 0)
+    assert torch.equal(idx, ri) and torch.equal(dist, rd)
+    check_knn(X, Ys, 6, p, k, idx.cpu().numpy(), dist.cpu().numpy(), f"chunked {mode} p={p} k={k}")
+    check_stats(X, Ys, 6, p, st, mode, pd=bool(pd))
+    if mode != "brute":
+        assert np.all(st[:, 1] > 32)  # seeds drawn in every chunk: several chunks ran
+    db.close()
+
+
 # ------------------------------------------------------------------ nearest-neighbour search
 def oracle_knn(X, Ys, w, p, k):
     idx, dist = native.nn_bruteforce(X, Ys, R.effective_band(X.shape[1], w), p, k)

@@ -184,12 +184,11 @@ def test_ragged_invalid_arguments(L, ctx, dbs):
 def test_ragged_uneven4096_full_size(L):
     """The uneven batch the benchmark times -- 4,096 random-walk queries, n uniform over
     {64, 128, 256, 512, 1024}, w = round(f n) with f in {0.05, 0.1, 0.2}, 20,000 series per
-    length, p = 1, 1-NN -- in its launch configuration (autotuned context, graph replay on four
-    streams): every query equals the search of its group alone, bit for bit, and the first query
+    length, p = 1, 1-NN -- in its launch configuration (graph replay on four streams, the
+    context's default choices): every query equals the search of its group alone, bit for bit, and the first query
     of every (length, band) group matches the oracle."""
     _say("ragged uneven batch, full size (4096 queries, 5 x 20000 series)")
     ctx2 = L.Ctx(0)
-    L.lbimp_ctx_set_option(ctx2, "autotune", 1)
     dbs64, qs, db_of, w = gen.make_ragged_workload()
     Xs = [f32(d) for d in dbs64]
     del dbs64
@@ -198,7 +197,7 @@ def test_ragged_uneven4096_full_size(L):
         offsets = np.zeros(len(qs) + 1, np.int64)
         offsets[1:] = np.cumsum([len(y) for y in qs])
         packed = to_dev(f32(np.concatenate(qs)))
-        L.lbimp_nn_search_ragged(ctx2, handles, packed, offsets, db_of, w, 1, 1, "improved")  # tunes, captures
+        L.lbimp_nn_search_ragged(ctx2, handles, packed, offsets, db_of, w, 1, 1, "improved")  # captures
         idx, dist, st = L.lbimp_nn_search_ragged(ctx2, handles, packed, offsets, db_of, w, 1, 1, "improved")
         idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
         Ys = [f32(y) for y in qs]

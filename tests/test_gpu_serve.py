@@ -34,8 +34,9 @@ def _alone(L, ctx, handles, r):
     return i.cpu().numpy()[0], d.cpu().numpy()[0]
 
 
-def _run(L, handles, reqs, budget, slots, max_batch):
-    ex = GpuExecutor(handles, slots=slots, max_batch=max_batch, kmax=10)
+def _run(L, handles, reqs, budget, slots, max_batch, bound=False):
+    ex = GpuExecutor(handles, slots=slots, max_batch=max_batch, kmax=10,
+                     workspace_limit=budget // slots if bound else 0)
     try:
         results, summary = serve(reqs, ex, budget_bytes=budget, max_batch=max_batch)
     finally:
@@ -43,11 +44,15 @@ def _run(L, handles, reqs, budget, slots, max_batch):
     return {r.rid: r for r in results}, summary
 
 
-@pytest.mark.parametrize("budget,slots,max_batch", [(8 << 30, 4, 256), (24 << 20, 3, 64)])
-def test_serving_results_equal_alone(L, ctx, workload, budget, slots, max_batch):
-    _say(f"serving 600 requests at 20k q/s, budget {budget >> 20} MiB, {slots} slots, batch <= {max_batch}")
+@pytest.mark.parametrize("budget,slots,max_batch,bound", [(8 << 30, 4, 256, False), (24 << 20, 3, 64, False),
+                                                           (6 << 20, 3, 128, True)])
+def test_serving_results_equal_alone(L, ctx, workload, budget, slots, max_batch, bound):
+    """With bound, each slot's workspace is limited to its share of the budget, so batches larger
+    than that search their databases in chunks of candidates."""
+    _say(f"serving 600 requests at 20k q/s, budget {budget >> 20} MiB, {slots} slots, batch <= {max_batch}, "
+         f"workspace bound {bound}")
     Xs, handles, reqs = workload
-    got, summary = _run(L, handles, reqs, budget, slots, max_batch)
+    got, summary = _run(L, handles, reqs, budget, slots, max_batch, bound)
     assert len(got) == len(reqs)
     assert summary["count"] == len(reqs) and summary["p99_ms"] >= summary["p50_ms"] > 0
     assert summary["workspace_bytes"] <= budget
@@ -82,9 +87,10 @@ def test_serving_batches_overlap_under_load(L, ctx, workload):
 def test_serving_full_size_sampled(L, ctx):
     """The serving workload the benchmark runs -- a resident 1,000,000 x 128 random-walk database
     (512 MB) and a 200,000 x 256 side database, w = round(0.1 n), k in {1, 5, 10} -- at 20k q/s
-    offered, with the benchmark's four slots, batches of at most 512 and a 16 GiB budget, after
-    pretuning: every result equals the same query searched alone, bit for bit, and the first
-    request of each database matches the oracle."""
+    offered, with the benchmark's four slots, batches of at most 512 and a 4 GiB budget (1 GiB of
+    workspace per slot, larger batches searched in chunks of candidates), after pretuning: every
+    result equals the same query searched alone, bit for bit, and the first request of each
+    database matches the oracle."""
     _say("serving full size: 1M x 128 and 200k x 256 databases, 400 requests at 20k q/s")
     dbs64, req = gen.make_serving_workload(20_000, 400)
     Xs = [f32(d) for d in dbs64]
@@ -92,15 +98,16 @@ def test_serving_full_size_sampled(L, ctx):
     handles = [L.Db(ctx, to_dev(X)) for X in Xs]
     reqs = [Request(rid=i, t_arrive=float(req["t"][i]), db=int(req["db"][i]), y=f32(req["y"][i]),
                     w=int(req["w"][i]), k=int(req["k"][i])) for i in range(len(req["t"]))]
-    ex = GpuExecutor(handles, slots=4, max_batch=512, kmax=10)
+    ex = GpuExecutor(handles, slots=4, max_batch=512, kmax=10, workspace_limit=1 << 30)
     try:
         ex.pretune(reqs[:200])
-        results, summary = serve(reqs, ex, budget_bytes=16 << 30, max_batch=512)
+        results, summary = serve(reqs, ex, budget_bytes=4 << 30, max_batch=512)
     finally:
         ex.close()
     try:
         got = {r.rid: r for r in results}
         assert len(got) == len(reqs) and summary["p99_ms"] >= summary["p50_ms"] > 0
+        assert summary["workspace_bytes"] <= 4 << 30
         for r in reqs:
             ai, ad = _alone(L, ctx, handles, r)
             assert np.array_equal(got[r.rid].idx, ai), r.rid

@@ -3,8 +3,9 @@
 The variant runs the same kernels on the library's fixed device scratch instead of the
 context's workspace.  Its outputs must equal lbimp_nn_search's bit for bit (and hence the
 oracle's, to the same tolerance); two calls in a row, the second smaller, check that the
-shared scratch left by one call does not leak into the next; a search too large for the
-scratch is refused before any work is enqueued; the context's workspace is never touched.
+shared scratch left by one call does not leak into the next; a search larger than the scratch
+runs in chunks of candidates and one that cannot fit even so is refused before any work is
+enqueued; the context's workspace is never touched.
 """
 import numpy as np
 import pytest
@@ -48,20 +49,24 @@ def test_noalloc_matches_search_on_two_calls(L, mode):
         ctx.close()
 
 
-def test_noalloc_refuses_a_search_larger_than_the_scratch(L):
-    _say("nn_search_noalloc over the scratch size")
+def test_noalloc_chunks_a_large_search_and_refuses_what_cannot_fit(L):
+    _say("nn_search_noalloc: a search larger than the scratch, then one that cannot fit")
     ctx = L.Ctx(0)
     X = _walks(100_000, 16, 2)
     db = L.Db(ctx, to_dev(X))
     try:
-        Yd = to_dev(_walks(100, 16, 3))  # about 12 Q N bytes = 120 MB > 64 MiB
+        # about 12 Q N bytes = 120 MB unchunked: searched in chunks of candidates that fit 64 MiB
+        Yd = to_dev(_walks(100, 16, 3))
+        i, d = L.lbimp_nn_search_noalloc(ctx, db, Yd, 2, 1, 1, "improved")
+        ri, rd, _ = L.lbimp_nn_search(ctx, db, Yd, 2, 1, 1, "improved", stats=False)
+        assert torch.equal(i, ri) and torch.equal(d, rd)
+        # 4,000 queries need 12 x 4000 x 2048 bytes even for the smallest chunk: refused, nothing run
         with pytest.raises(L.LbimpError) as e:
-            L.lbimp_nn_search_noalloc(ctx, db, Yd, 2, 1, 1, "improved")
+            L.lbimp_nn_search_noalloc(ctx, db, to_dev(_walks(4000, 16, 4)), 2, 1, 1, "improved")
         assert e.value.code == L.LBIMP_E_NOMEM
         # a search that fits still runs afterwards
         i, d = L.lbimp_nn_search_noalloc(ctx, db, Yd[:4], 2, 1, 1, "improved")
-        ri, rd, _ = L.lbimp_nn_search(ctx, db, Yd[:4], 2, 1, 1, "improved", stats=False)
-        assert torch.equal(i, ri) and torch.equal(d, rd)
+        assert torch.equal(i, ri[:4]) and torch.equal(d, rd[:4])
     finally:
         torch.cuda.synchronize()
         db.close()
