@@ -501,6 +501,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-shapes", action="store_true", help="skip the shape-signature measurement")
     ap.add_argument("--no-triangle", action="store_true", help="skip the App. B triangle-inequality workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the headline with the context's default choices (with --set: profiling A/B)")
+    ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE",
+                    help="context option for the headline searches (repeatable), e.g. lbi_buckets=1")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
     ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle", "pd", "abandon",
@@ -574,7 +578,10 @@ def main():
     Yd = torch.from_numpy(Ys).cuda()
     torch.cuda.synchronize()
     # the autotuner picks seeds, tiling and kernels for each mode/p on its first (warm-up) call
-    L.lbimp_ctx_set_option(ctx, "autotune", 1)
+    L.lbimp_ctx_set_option(ctx, "autotune", 0 if args.no_autotune else 1)
+    for kv in args.set:
+        name, value = kv.split("=", 1)
+        L.lbimp_ctx_set_option(ctx, name, int(value))
 
     log("timing two-pass p=1")
     imp = time_mode(L, ctx, db, Yd, w, 1, "improved", args.steps, args.warmup)
@@ -691,6 +698,7 @@ def main():
                            dtw_fraction=float(st[:, 4].sum() / (N * Q)),
                            abandoned_fraction_of_dtw=float(st[:, 5].sum() / max(1, st[:, 4].sum()))),
         "stage_ms_p1": stages,
+        "headline_options": {"autotune": not args.no_autotune, "set": args.set},
         "accuracy_vs_oracle": accuracy,
         "lb_single_query_hbm": lbg,
         "pd_prefilter": pdb,

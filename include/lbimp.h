@@ -87,7 +87,8 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
 /* Tuning options of a context (they change speed, never results):
  *   "seeds"         1..64 (default 32): candidates of smallest LB_Keogh whose DTW sets the
  *                   initial threshold of lbimp_nn_search (at least k are used);
- *   "lbi_pipeline"  0/1 (default 1): software-pipelined loads in the LB_Improved pass;
+ *   "lbi_pipeline"  0/1 (default 1): the LB_Improved pass loads the next block of the
+ *                   candidates' rows while it computes one (bands up to w = 31; 0: loads in batches);
  *   "dtw_group_per_pair"  0/1 (default 0): lbimp_dtw_band computes each DTW with a group of
  *                   lanes along anti-diagonals (the kernel of the seeding stage) instead of
  *                   one lane per pair; bands with w > 63 always use the anti-diagonal kernel;
@@ -118,7 +119,11 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *   "lbi_abandon"   0/1 (default 0): early abandoning inside the LB_Improved pass (Sec. 10 of
  *                   the paper tried it on the CPU): a wave stops a pair's sum once it reaches the
  *                   threshold -- the register kernel when all 64 pairs of a wave have, the
- *                   wave-per-pair kernel of wide bands before the second half of a pair's sum.
+ *                   wave-per-pair kernel of wide bands before the second half of a pair's sum;
+ *   "lbi_buckets"   0/1 (default 0): the survivors of LB_Keogh are listed per query in buckets
+ *                   of candidates (about 2 MiB of rows each) and LB_Improved walks them bucket by
+ *                   bucket, each bucket on one XCD, so the rows it gathers for every query stay
+ *                   in that XCD's L2; partly filled work items cost instructions in exchange.
  * Returns LBIMP_E_INVALID for an unknown name or an out-of-range value. */
 int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
 
@@ -242,9 +247,9 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
  * "autotune" set, those calls tune a shape they meet for the first time by themselves.
  * choice: host [LBIMP_TUNE_KNOBS] or NULL, receives {seeds, sweep_shape, lbi_pipeline,
  * survivors' DTW group-per-pair, seeding DTW lane-per-pair, abandon bound with the LB_Keogh
- * tail, pass 0 with the piecewise-sum bound, early abandoning in LB_Improved}.  Waits for the
- * stream. */
-#define LBIMP_TUNE_KNOBS 8
+ * tail, pass 0 with the piecewise-sum bound, early abandoning in LB_Improved, LB_Improved over
+ * survivor lists bucketed by candidate range}.  Waits for the stream. */
+#define LBIMP_TUNE_KNOBS 9
 int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                    int32_t k, int32_t mode, int32_t *choice);
 

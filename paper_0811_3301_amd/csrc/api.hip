@@ -107,13 +107,14 @@ struct lbimp_ctx {
     bool timing = false;
     bool timed_valid = false;
     int seeds = 32;             // option "seeds"
-    bool lbi_pipeline = true;   // option "lbi_pipeline"
+    int lbi_pipeline = 1;       // option "lbi_pipeline"
     bool dtw_low_latency = false;  // option "dtw_group_per_pair" (lbimp_dtw_band only)
     int sweep_shape = 0;           // option "sweep_shape"
     bool use_graph = true;         // option "graph" (lbimp_nn_search_ragged)
     int ragged_streams = kPoolStreams;  // option "ragged_streams"
     bool pd_prefilter = false;          // option "pd_prefilter"
     bool lbi_abandon = false;           // option "lbi_abandon"
+    bool lbi_buckets = false;           // option "lbi_buckets"
     size_t ws_limit = 0;                // option "workspace_limit" (bytes, 0: none)
     // ragged batches: stream pool, captured graph, pinned staging of the grouping metadata
     hipStream_t graph_stream = nullptr;
@@ -202,13 +203,14 @@ namespace {
 // Choices that change speed, never results.
 struct Knobs {
     int seeds;          // seeding DTWs (at least k are used)
-    bool lbi_pipeline;  // pipelined loads in the register LB_Improved kernel
+    int lbi_pipeline;   // blocks loaded ahead by the register LB_Improved kernel (0 or 1)
     int sweep_shape;    // tiling of the LB_Keogh sweep
     bool dtw_group;     // survivors' DTW with a group of lanes per pair (else a lane per pair)
     bool seed_lane;     // seeding DTWs with a lane per pair (else a group of lanes per pair)
     bool cascade;       // abandon on the row minimum plus the LB_Keogh terms still to come
     bool pd = false;    // pass 0: piecewise-sum bound of every candidate, LB_Keogh only of its survivors
     bool lbi_abandon = false;  // early abandoning inside the LB_Improved pass
+    bool lbi_buckets = false;  // LB_Improved over bucketed survivor lists (XCD-local row reuse)
 };
 
 struct SearchSpec {  // Q queries of one length against one database
@@ -229,13 +231,15 @@ struct SearchDims {
     int n, n4, ldq, wb, qg, S, WL, k, p;
     int64_t N, Np, Q, Qp, ldres, nw;
     int64_t C, nchunks;  // candidates per chunk (a multiple of kChunkAlign unless the whole database) and chunk count
+    int64_t bs;          // candidates per bucket of the LB_Improved survivor lists
+    int nb;              // buckets per chunk (1: the lists are not bucketed)
     size_t ring_bytes;  // strip-boundary scratch of the wide-band DTW
     bool brute, improved, from_minima, pd;
 };
 
 struct SearchBufs {
     float *Ue, *Le, *S1, *ring;
-    int *seeds, *list0, *list1, *list2, *counters;
+    int *seeds, *list0, *list1, *list2, *counters, *cntb;
     u64 *best, *thr, *res, *wmin;
     long long *prefix, *tot;
     double *qpd;
@@ -254,6 +258,11 @@ static void chunk_dims(const SearchSpec &sp, int64_t C, SearchDims &d) {
     d.nw = d.pd ? pd_scan_waves(d.C) : sweep_waves(sp.kn.sweep_shape, d.C, sp.Q);
     // seeds come from the per-wave minima of the sweep once there are enough of them
     d.from_minima = !d.brute && d.nw >= 4 * (int64_t)kMaxSeeds;
+    // LB_Improved survivors bucketed by candidate range: about 2 MiB of rows per bucket, so that
+    // one bucket's rows stay in an XCD's L2 while the pairs of every query read them
+    const int64_t span = compact_wave_span();
+    d.bs = std::max<int64_t>(span, ((int64_t)(2 << 20) / (4 * (int64_t)d.n)) / span * span);
+    d.nb = (d.improved && sp.kn.lbi_buckets && d.C > d.bs) ? (int)((d.C + d.bs - 1) / d.bs) : 1;
 }
 
 void layout(Carver &c, const SearchDims &d, SearchBufs &b);
@@ -309,8 +318,9 @@ void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
     b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.C);
     b.list2 = (d.improved && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
     b.counters = c.take<int>((size_t)d.Q * kCounters);  // cnt1, cnt2, rescnt, abandoned, cnt0 ([kCounters][Q])
+    b.cntb = (d.nb > 1 && any) ? c.take<int>((size_t)d.Q * d.nb) : nullptr;  // bucketed pass-1 counts [nb][Q]
     b.tot = d.nchunks > 1 ? c.take<long long>((size_t)d.Q * 3) : nullptr;  // cnt1, cnt2, cnt0 over all chunks
-    b.prefix = c.take<long long>((size_t)d.Q + 1);
+    b.prefix = c.take<long long>((size_t)d.Q * d.nb + 1);
     b.wmin = (d.from_minima && any) ? c.take<u64>((size_t)d.Q * d.nw) : nullptr;
     b.ring = (d.ring_bytes && any) ? c.take<float>(d.ring_bytes / sizeof(float)) : nullptr;
 }
@@ -433,11 +443,21 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
                 HIPTRY(launch_lbk_gather(p, db->rows, n, qd, PairList{b.list0, d.C, cnt0, 0}, b.prefix, Q, grid, S1v,
                                          d.Np, s));
             }
-            HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt1, s, c0));
+            if (d.nb > 1) {  // survivors bucketed by candidate range for the LB_Improved pass
+                HIPTRY(launch_fill_i32(b.cntb, 0, Q * d.nb, s));
+                HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt1, s, c0, d.bs, b.cntb));
+            } else {
+                HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt1, s, c0));
+            }
             stage_first(5);
             PairList dl{b.list1, d.C, cnt1, 0};
             if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
-                HIPTRY(launch_items_prefix(cnt1, 0, Q, d.WL, b.prefix, s));
+                if (d.nb > 1) {
+                    dl = PairList{b.list1, d.C, b.cntb, 0, 0, d.nb, d.bs, Q};
+                    HIPTRY(launch_items_prefix(b.cntb, 0, Q * d.nb, d.WL, b.prefix, s));
+                } else {
+                    HIPTRY(launch_items_prefix(cnt1, 0, Q, d.WL, b.prefix, s));
+                }
                 HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, S1v, d.Np, b.prefix, Q, nullptr,
                                   grid, T, b.list2, d.C, cnt2, nullptr, sp.kn.lbi_pipeline, sp.kn.lbi_abandon, s));
                 dl = PairList{b.list2, d.C, cnt2, 0};
@@ -465,8 +485,9 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
 }
 
 static Knobs ctx_knobs(const lbimp_ctx *ctx) {
-    return Knobs{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false, true, ctx->pd_prefilter,
-                 ctx->lbi_abandon};
+    Knobs k{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false, true, ctx->pd_prefilter, ctx->lbi_abandon};
+    k.lbi_buckets = ctx->lbi_buckets;
+    return k;
 }
 
 static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int mode) {
@@ -474,12 +495,14 @@ static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int
 }
 
 static Knobs knobs_of(const std::array<int, kTuneKnobs> &v) {
-    return Knobs{v[0], v[2] != 0, v[1], v[3] != 0, v[4] != 0, v[5] != 0, v[6] != 0, v[7] != 0};
+    Knobs k{v[0], v[2], v[1], v[3] != 0, v[4] != 0, v[5] != 0, v[6] != 0, v[7] != 0};
+    k.lbi_buckets = v[8] != 0;
+    return k;
 }
 
 static std::array<int, kTuneKnobs> knob_values(const Knobs &k) {
-    return {k.seeds, k.sweep_shape, k.lbi_pipeline ? 1 : 0, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0,
-            k.cascade ? 1 : 0, k.pd ? 1 : 0, k.lbi_abandon ? 1 : 0};
+    return {k.seeds, k.sweep_shape, k.lbi_pipeline, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0,
+            k.cascade ? 1 : 0, k.pd ? 1 : 0, k.lbi_abandon ? 1 : 0, k.lbi_buckets ? 1 : 0};
 }
 
 // The tuned choice for this batch shape if there is one, else the context's options.
@@ -507,17 +530,19 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     size_t search_bytes = 0;
     for (int sd : seed_opts)
         for (int sh : shape_opts)
-            for (bool pdv : {false, true}) {
-                SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr,
-                              Knobs{sd, true, sh, false, false, true, pdv}};
-                sp.ws_limit = ctx->ws_limit;
-                SearchDims d;
-                if (int r = dims_of(sp, ctx->num_cu, d)) return r;
-                SearchBufs b;
-                Carver cv{nullptr};
-                layout(cv, d, b);
-                search_bytes = std::max(search_bytes, cv.off);
-            }
+            for (bool pdv : {false, true})
+                for (bool bk : {false, true}) {
+                    SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr,
+                                  Knobs{sd, 1, sh, false, false, true, pdv}};
+                    sp.kn.lbi_buckets = bk;
+                    sp.ws_limit = ctx->ws_limit;
+                    SearchDims d;
+                    if (int r = dims_of(sp, ctx->num_cu, d)) return r;
+                    SearchBufs b;
+                    Carver cv{nullptr};
+                    layout(cv, d, b);
+                    search_bytes = std::max(search_bytes, cv.off);
+                }
     auto carve_tune = [&](Carver &c, float *&qb, int64_t *&ob, int64_t *&ib, float *&db_) {
         qb = qdev ? nullptr : c.take<float>((size_t)Q * n);
         ob = qdev ? nullptr : c.take<int64_t>((size_t)Q);
@@ -611,12 +636,17 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     }
     if (improved && wb <= kLbiRegMaxW) {
         Knobs kn = best;
-        kn.lbi_pipeline = !kn.lbi_pipeline;
-        if (int r = consider(kn)) return r;
+        for (int depth = 0; depth <= 1; ++depth) {
+            kn.lbi_pipeline = depth;
+            if (int r = consider(kn)) return r;
+        }
     }
     if (improved) {
         Knobs kn = best;
         kn.lbi_abandon = !kn.lbi_abandon;
+        if (int r = consider(kn)) return r;
+        kn = best;
+        kn.lbi_buckets = !kn.lbi_buckets;  // pays where the rows of the survivors come from HBM or MALL
         if (int r = consider(kn)) return r;
     }
     if (!brute) {
@@ -846,7 +876,8 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         if (value < 1 || value > kMaxSeeds) return fail(LBIMP_E_INVALID, "seeds must be in [1, %d]", kMaxSeeds);
         ctx->seeds = (int)value;
     } else if (!strcmp(name, "lbi_pipeline")) {
-        ctx->lbi_pipeline = value != 0;
+        if (value < 0 || value > 1) return fail(LBIMP_E_INVALID, "lbi_pipeline must be 0 or 1");
+        ctx->lbi_pipeline = (int)value;
     } else if (!strcmp(name, "dtw_group_per_pair")) {
         ctx->dtw_low_latency = value != 0;
     } else if (!strcmp(name, "graph")) {
@@ -861,6 +892,8 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         ctx->pd_prefilter = value != 0;
     } else if (!strcmp(name, "lbi_abandon")) {
         ctx->lbi_abandon = value != 0;
+    } else if (!strcmp(name, "lbi_buckets")) {
+        ctx->lbi_buckets = value != 0;
     } else if (!strcmp(name, "workspace_limit")) {
         if (value < 0) return fail(LBIMP_E_INVALID, "workspace_limit must be >= 0");
         ctx->ws_limit = (size_t)value;
@@ -1294,7 +1327,8 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         mix((uint64_t)(specs[g].k * 2 + (plan.mixed_k[g] ? 1 : 0)));
         const Knobs &kn = specs[g].kn;
         mix((uint64_t)(kn.seeds * 1000000 + kn.sweep_shape * 10000 + kn.lbi_pipeline * 1000 + kn.dtw_group * 100 +
-                       kn.seed_lane * 10 + kn.cascade + (kn.pd ? 100000000 : 0) + (kn.lbi_abandon ? 200000000 : 0)));
+                       kn.seed_lane * 10 + kn.cascade + (kn.pd ? 100000000 : 0) + (kn.lbi_abandon ? 200000000 : 0) +
+                       (kn.lbi_buckets ? 400000000 : 0)));
     }
     if (!ctx->use_graph && width <= 1) {
         if (int r = enqueue_all(ctx->stream)) return r;

@@ -16,24 +16,66 @@ __device__ __forceinline__ u64 make_key(float v, int c) {
 // so no shared counter is contended.  With a fixed pair count per query the item maps to its
 // query arithmetically; otherwise by binary search over the per-query item prefix.  Every
 // block leaves the loop once its next item is past the total, so the grid always drains.
+// Bucketed lists (pl.nb > 1; prefix over the nb * Q (bucket, query) slots, bucket-major):
+// blocks are dealt to the 8 XCDs in turn (block g on XCD g % 8), so XCD x takes buckets x,
+// x + 8, x + 16, ... and its blocks stride through the items of one bucket before the next;
+// bk names the bucket of the last item.
 struct ItemCursor {
     long long next, stride, total;
     long long ipq;  // items per query when every query has the same pair count, else 0
     const long long *prefix;
     int64_t Q;
+    int nb, bstep;
+    int bk = 0;
 
     __device__ ItemCursor(const PairList &pl, const long long *prefix_, int64_t Q_, int batch)
-        : next(blockIdx.x), stride(gridDim.x), prefix(prefix_), Q(Q_) {
+        : next(blockIdx.x), stride(gridDim.x), prefix(prefix_), Q(Q_), nb(pl.nb), bstep(1) {
         if (!pl.cnt) {
             ipq = (pl.fixed + batch - 1) / batch;
             total = Q * ipq;
         } else {
             ipq = 0;
-            total = prefix[Q];
+            total = prefix[(int64_t)nb * Q];
+        }
+        if (nb > 1 && gridDim.x >= 8 && gridDim.x % 8 == 0) {
+            bk = (int)(blockIdx.x % 8);
+            next = blockIdx.x / 8;
+            stride = gridDim.x / 8;
+            bstep = 8;
+        } else if (nb > 1) {
+            bk = 0;
         }
     }
 
+    // largest v in [lo, hi) with prefix[v] <= item
+    __device__ int64_t slot_of(long long item, int64_t lo, int64_t hi) const {
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (prefix[mid] <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        return lo;
+    }
+
     __device__ bool get(int64_t &q, long long &b) {
+        if (nb > 1) {  // next is the item offset within bucket bk
+            while (bk < nb) {
+                const long long lo = prefix[(int64_t)bk * Q], range = prefix[(int64_t)(bk + 1) * Q] - lo;
+                if (next < range) {
+                    const long long item = lo + next;
+                    next += stride;
+                    const int64_t v = slot_of(item, (int64_t)bk * Q, (int64_t)(bk + 1) * Q);
+                    q = v - (int64_t)bk * Q;
+                    b = item - prefix[v];
+                    return true;
+                }
+                next -= range;
+                bk += bstep;
+            }
+            return false;
+        }
         if (next >= total) return false;
         const long long item = next;
         next += stride;
@@ -42,26 +84,18 @@ struct ItemCursor {
             b = item - q * ipq;
             return true;
         }
-        int64_t lo = 0, hi = Q;  // largest q with prefix[q] <= item
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (prefix[mid] <= item)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        q = lo;
-        b = item - prefix[lo];
+        q = slot_of(item, 0, Q);
+        b = item - prefix[q];
         return true;
     }
 };
 
-__device__ __forceinline__ int pair_count(const PairList &pl, int64_t q) {
-    return pl.cnt ? pl.cnt[q] : (int)pl.fixed;
+__device__ __forceinline__ int pair_count(const PairList &pl, int64_t q, int bk = 0) {
+    return pl.cnt ? pl.cnt[(int64_t)bk * pl.cq + q] : (int)pl.fixed;
 }
 
-__device__ __forceinline__ int pair_cand(const PairList &pl, int64_t q, long long j) {
-    return pl.list ? pl.list[q * pl.ldl + j] : (int)(pl.base + j);
+__device__ __forceinline__ int pair_cand(const PairList &pl, int64_t q, long long j, int bk = 0) {
+    return pl.list ? pl.list[q * pl.ldl + (int64_t)bk * pl.bs + j] : (int)(pl.base + j);
 }
 
 
@@ -198,7 +232,7 @@ struct LbiArgs {
     int64_t ldl2;
     int *cnt2;
     float *out_root;
-    bool pipeline;  // software-pipelined staging (more registers, fewer exposed load latencies)
+    int pipeline;   // blocks loaded ahead in the register kernel: 0 or 1 (more registers, fewer exposed latencies)
     bool abandon;   // early abandoning: stop once the partial bound reaches the threshold (thr set)
 };
 

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
             cur_q = q;
         }
         const long long jj = b * 64 + lane;
-        const int cl = jj < pair_count(a.pl, q) ? pair_cand(a.pl, q, jj) : -1;
+        const int cl = jj < pair_count(a.pl, q, items.bk) ? pair_cand(a.pl, q, jj, items.bk) : -1;
         bool active = cl >= 0;
         const int c = active ? cl : 0;
         const float *x = a.rows + (int64_t)c * n;

@@ -129,7 +129,7 @@ void k_dtw_strip(DtwArgs a, int w, float *__restrict__ ring_base, int rb_log2) {
             cur_q = q;
         }
         const long long jj = b * 64 + lane;
-        const int cl = jj < pair_count(a.pl, q) ? pair_cand(a.pl, q, jj) : -1;
+        const int cl = jj < pair_count(a.pl, q, items.bk) ? pair_cand(a.pl, q, jj, items.bk) : -1;
         bool active = cl >= 0;
         const int c = active ? cl : 0;
         const float *x = a.rows + (int64_t)c * n;

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(64) void k_dtw_wavereg(DtwArgs a, int w, int LP) {
     ItemCursor items(a.pl, a.prefix, a.Q, G);
     while (items.get(q, b)) {
         const long long jj = b * G + g;
-        const int cl = jj < pair_count(a.pl, q) ? pair_cand(a.pl, q, jj) : -1;
+        const int cl = jj < pair_count(a.pl, q, items.bk) ? pair_cand(a.pl, q, jj, items.bk) : -1;
         const bool active0 = cl >= 0;
         const int c = active0 ? cl : 0;
         __syncthreads();
@@ -160,8 +160,8 @@ __global__ __launch_bounds__(64) void k_dtw_wavereg_r(DtwArgs a, int w) {
     long long b;
     ItemCursor items(a.pl, a.prefix, a.Q, 1);
     while (items.get(q, b)) {
-        if (b >= pair_count(a.pl, q)) continue;
-        const int c = pair_cand(a.pl, q, b);
+        if (b >= pair_count(a.pl, q, items.bk)) continue;
+        const int c = pair_cand(a.pl, q, b, items.bk);
         __syncthreads();
         if (q != cur_q) {
             const float *y = a.qd.Y + q * a.qd.ldy;

@@ -60,8 +60,12 @@ hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int
                                int64_t nw, int *seeds, hipStream_t s, int64_t c0 = 0);
 
 // list[q][*] <- candidates c0 <= c < N with key(S1[q][c], c) < thr[q]; cnt[q] += number kept.
+// Bucketed (cntb given): candidate c goes to bucket k = (c - c0) / bs, at list[q][k * bs + pos]
+// with pos counted in cntb[k * Q + q]; bs must be a multiple of compact_wave_span().
 hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, const unsigned long long *thr,
-                          int *list, int64_t ldl, int *cnt, hipStream_t s, int64_t c0 = 0);
+                          int *list, int64_t ldl, int *cnt, hipStream_t s, int64_t c0 = 0, int64_t bs = 0,
+                          int *cntb = nullptr);
+int64_t compact_wave_span();
 
 // prefix[0] = 0, prefix[q+1] = prefix[q] + ceil(count_q / batch), count_q = cnt[q] or `fixed`.
 hipError_t launch_items_prefix(const int *cnt, int64_t fixed, int64_t Q, int batch, long long *prefix,
@@ -84,12 +88,19 @@ hipError_t launch_pd_scan(int p, const double *pd, int64_t N, int n, const doubl
                           int64_t cbase = 0);
 
 // Pair list description for the persistent second-pass and DTW kernels.
+// Bucketed lists (nb > 1): the candidates of each query are split by index range into nb
+// buckets; bucket k of query q holds its pairs at list[q * ldl + k * bs + j] and counts them in
+// cnt[k * cq + q].  The persistent kernels then walk the work bucket by bucket, each bucket on
+// one XCD, so that the rows of a bucket, read by the pairs of every query, stay in that XCD's L2.
 struct PairList {
     const int *list;     // [Q][ldl] candidate ids, or nullptr for "candidate = base + position"
     int64_t ldl;
-    const int *cnt;      // [Q] counts, or nullptr for `fixed` pairs per query
+    const int *cnt;      // [Q] counts ([nb][cq] when bucketed), or nullptr for `fixed` pairs per query
     int64_t fixed;
     int64_t base = 0;
+    int nb = 1;          // buckets
+    int64_t bs = 0;      // list entries per bucket
+    int64_t cq = 0;      // row stride of the bucketed counts (the query count)
 };
 
 struct QueryData {
@@ -110,7 +121,7 @@ int lbi_batch(int n, int w);
 hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, QueryData qd, PairList pl, const float *S1,
                       int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
-                      bool pipeline, bool abandon, hipStream_t s);
+                      int pipeline, bool abandon, hipStream_t s);
 
 // LB_Keogh^p of the pairs of pl (the pass-0 survivors), reading each candidate's row: S1[q][c]
 // receives the bound.  Items hold lbk_gather_batch() pairs; prefix is launch_items_prefix over

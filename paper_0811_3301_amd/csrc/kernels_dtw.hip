@@ -58,8 +58,8 @@ __global__ __launch_bounds__(64) void k_lbi(const float *__restrict__ rows, int 
             cur_q = q;
         }
         const long long j = b * WL + lane;
-        const bool active = lane < WL && j < pair_count(pl, q);
-        const int c = active ? pair_cand(pl, q, j) : 0;
+        const bool active = lane < WL && j < pair_count(pl, q, items.bk);
+        const int c = active ? pair_cand(pl, q, j, items.bk) : 0;
         const float *x = rows + (int64_t)c * n;
         const int hl = lane < WL ? lane : 0;
         if (lane < WL) {
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(64) void k_lbi(const float *__restrict__ rows, int 
 hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, QueryData qd, PairList pl, const float *S1,
                       int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
-                      bool pipeline, bool abandon, hipStream_t s) {
+                      int pipeline, bool abandon, hipStream_t s) {
     if (w <= kLbiRegMaxW || lbi_wave_supported(n, w)) {
         LbiArgs a{rows, db_bytes, n, qd, pl, S1, ldS, prefix, Q, ctr, thr, list2, ldl2, cnt2, out_root, pipeline,
                   abandon};
@@ -164,9 +164,9 @@ __global__ __launch_bounds__(64) void k_dtw_wave(const float *__restrict__ rows,
     long long b;
     ItemCursor items(pl, prefix, Q, 1);
     while (items.get(q, b)) {
-        const bool valid = b < pair_count(pl, q);
+        const bool valid = b < pair_count(pl, q, items.bk);
         if (!valid) continue;
-        const int c = pair_cand(pl, q, b);
+        const int c = pair_cand(pl, q, b, items.bk);
         const float *sx = rows + (int64_t)c * n;
         const float *sy = qd.Y + q * qd.ldy;
         __syncthreads();

@@ -453,10 +453,12 @@ hipError_t launch_select_seeds(float *S1, int64_t ldS, int64_t N, int64_t Q, int
 // ------------------------------------------------------------------ compaction
 // Strict test of Algorithms 2 and 3 on the (value, index) key: a candidate whose bound key is
 // not below the threshold key can at best tie, and a tie goes to the smaller index.
-// Each wave covers 64*CH candidates: one ballot per chunk, one atomicAdd per wave.
+// Each wave covers 64*CH candidates: one ballot per chunk, one atomicAdd per block (per bucket
+// of the block when the list is bucketed: cntb given, buckets of bs candidates counted from c0).
 __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, int64_t ldS, int64_t c0, int64_t N,
                                                   const unsigned long long *__restrict__ thr, int *__restrict__ list,
-                                                  int64_t ldl, int *__restrict__ cnt) {
+                                                  int64_t ldl, int *__restrict__ cnt, int64_t bs, int *__restrict__ cntb,
+                                                  int64_t cq) {
     constexpr int CH = 16;
     __shared__ int wtot[4];
     __shared__ int wbase[4];
@@ -486,11 +488,30 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, i
     if (lane == 0) wtot[wave] = total;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int sum = wtot[0] + wtot[1] + wtot[2] + wtot[3];
-        int pos = sum ? atomicAdd(&cnt[q], sum) : 0;
-        for (int wv = 0; wv < 4; ++wv) {
-            wbase[wv] = pos;
-            pos += wtot[wv];
+        if (!cntb) {
+            const int sum = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+            int pos = sum ? atomicAdd(&cnt[q], sum) : 0;
+            for (int wv = 0; wv < 4; ++wv) {
+                wbase[wv] = pos;
+                pos += wtot[wv];
+            }
+        } else {
+            // consecutive waves of one bucket share an atomic; list positions start at k * bs
+            const int64_t blk0 = c0 + (int64_t)blockIdx.x * 4 * 64 * CH;
+            int tot = 0;
+            for (int wv = 0; wv < 4;) {
+                const int64_t k = (blk0 + (int64_t)wv * 64 * CH - c0) / bs;
+                int sum = 0, w2 = wv;
+                while (w2 < 4 && (blk0 + (int64_t)w2 * 64 * CH - c0) / bs == k) sum += wtot[w2++];
+                int pos = sum ? atomicAdd(&cntb[k * cq + q], sum) : 0;
+                pos += (int)(k * bs);
+                for (; wv < w2; ++wv) {
+                    wbase[wv] = pos;
+                    pos += wtot[wv];
+                }
+                tot += sum;
+            }
+            if (tot) atomicAdd(&cnt[q], tot);
         }
     }
     __syncthreads();
@@ -506,13 +527,16 @@ __global__ __launch_bounds__(256) void k_compact(const float *__restrict__ S1, i
 }
 
 hipError_t launch_compact(const float *S1, int64_t ldS, int64_t N, int64_t Q, const unsigned long long *thr,
-                          int *list, int64_t ldl, int *cnt, hipStream_t s, int64_t c0) {
+                          int *list, int64_t ldl, int *cnt, hipStream_t s, int64_t c0, int64_t bs, int *cntb) {
     if (N <= c0 || Q == 0) return hipSuccess;
+    if (cntb && (bs <= 0 || bs % (64 * 16) != 0)) return hipErrorInvalidValue;  // a bucket is whole waves
     int64_t per_block = 4 * 64 * 16;
     dim3 grid((unsigned)((N - c0 + per_block - 1) / per_block), (unsigned)Q);
-    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, S1, ldS, c0, N, thr, list, ldl, cnt);
+    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, S1, ldS, c0, N, thr, list, ldl, cnt, bs, cntb, Q);
     return hipGetLastError();
 }
+
+int64_t compact_wave_span() { return 64 * 16; }
 
 // ------------------------------------------------------------------ work-item prefix
 __global__ __launch_bounds__(1024) void k_items_prefix(const int *__restrict__ cnt, int64_t fixed, int64_t Q,

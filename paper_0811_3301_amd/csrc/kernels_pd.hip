@@ -193,13 +193,13 @@ __global__ __launch_bounds__(64) void k_lbk_gather(const float *__restrict__ row
             __syncthreads();
             cur_q = q;
         }
-        const int count = pair_count(pl, q);
+        const int count = pair_count(pl, q, items.bk);
         int c[kGatherPairs];
         const float *x[kGatherPairs];
 #pragma unroll
         for (int g = 0; g < kGatherPairs; ++g) {
             const long long j = b * kGatherPairs + g;
-            c[g] = j < count ? pair_cand(pl, q, j) : -1;
+            c[g] = j < count ? pair_cand(pl, q, j, items.bk) : -1;
             x[g] = rows + (int64_t)(c[g] < 0 ? 0 : c[g]) * n;
         }
         float acc[kGatherPairs];

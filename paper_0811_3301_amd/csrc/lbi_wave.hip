@@ -153,8 +153,8 @@ __global__ __launch_bounds__(64) void k_lbi_wave(LbiArgs a, int w) {
             cur_q = q;
         }
         const long long j0 = b * 64;
-        const int cnt = (int)min(64ll, (long long)pair_count(a.pl, q) - j0);
-        const int c_mine = lane < cnt ? pair_cand(a.pl, q, j0 + lane) : 0;
+        const int cnt = (int)min(64ll, (long long)pair_count(a.pl, q, items.bk) - j0);
+        const int c_mine = lane < cnt ? pair_cand(a.pl, q, j0 + lane, items.bk) : 0;
         const float s1_mine = lane < cnt ? a.S1[q * a.ldS + c_mine] : 0.f;
         const bool abandon = a.abandon && a.thr && !a.out_root;
         const u64 tq = a.thr ? a.thr[q] : kNoKey;

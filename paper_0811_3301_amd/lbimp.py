@@ -67,7 +67,8 @@ SIGNATURES = {
     "lbimp_autotune": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32)]),
     "lbimp_ctx_copy_tuning": (ctypes.c_int, [_vp, _vp]),
 }
-TUNE_KNOBS = ("seeds", "sweep_shape", "lbi_pipeline", "dtw_group", "seed_lane", "cascade", "pd", "lbi_abandon")
+TUNE_KNOBS = ("seeds", "sweep_shape", "lbi_pipeline", "dtw_group", "seed_lane", "cascade", "pd", "lbi_abandon",
+              "lbi_buckets")
 
 _lib = None
 

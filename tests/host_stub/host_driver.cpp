@@ -92,6 +92,7 @@ static void ragged_batches() {
         for (int mode = LBIMP_MODE_BRUTE; mode <= LBIMP_MODE_IMPROVED; ++mode)
             for (int graph : {1, 0}) {
                 OK(lbimp_ctx_set_option(ctx, "graph", graph));
+                OK(lbimp_ctx_set_option(ctx, "lbi_buckets", graph));
                 OK(lbimp_ctx_set_option(ctx, "autotune", 0));
                 OK(lbimp_nn_search_ragged(ctx, dbs, 2, packed, off.data(), db_of.data(), w.data(), Q, p, k.data(), mode,
                                           idx, dist, st.data()));
@@ -141,6 +142,8 @@ static void chunked_and_noalloc() {
                 for (int pd : {0, 1})
                     for (int p : {1, 2, LBIMP_P_INF}) {
                         OK(lbimp_ctx_set_option(ctx, "pd_prefilter", pd));
+                        OK(lbimp_ctx_set_option(ctx, "lbi_buckets", ((p & 3) + pd + k) & 1));
+                        OK(lbimp_ctx_set_option(ctx, "lbi_pipeline", ((p & 3) + mode) & 1));
                         OK(lbimp_nn_search(ctx, db, qs, Q, 13, p, k, mode, idx, dist, st.data()));
                         check_stats(st, Q, N, "chunked");
                         const long long a0 = hip_stub_allocations();
@@ -195,6 +198,7 @@ static void invalid_arguments() {
     CHECK(lbimp_ctx_set_option(ctx, "no such option", 1) == LBIMP_E_INVALID, "unknown option accepted");
     CHECK(lbimp_ctx_set_option(ctx, "workspace_limit", -1) == LBIMP_E_INVALID, "negative bound accepted");
     CHECK(lbimp_ctx_set_option(ctx, "seeds", 65) == LBIMP_E_INVALID, "65 seeds accepted");
+    CHECK(lbimp_ctx_set_option(ctx, "lbi_pipeline", 2) == LBIMP_E_INVALID, "pipeline depth 2 accepted");
     // k above N: every slot past the N neighbours is empty, not an error
     OK(lbimp_nn_search(ctx, db, x, 1, 3, 1, 64, 2, idx, dist, nullptr));
     // an empty database

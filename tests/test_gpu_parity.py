@@ -271,6 +271,53 @@ def test_nn_search_lbi_abandon(L, ctx, n, w, p, k):
     db.close()
 
 
+@pytest.mark.parametrize("n,w,N", [(128, 13, 9000), (256, 26, 5000), (64, 6, 20000), (300, 80, 6000), (512, 51, 4000),
+                                   (2300, 600, 2100)])
+@pytest.mark.parametrize("p,k", [(1, 1), (2, 3), (INF, 2)])
+def test_nn_search_lbi_buckets(L, ctx, n, w, N, p, k):
+    """LB_Improved over survivor lists bucketed by candidate range (walked bucket by bucket, one
+    XCD per bucket): the same pairs are bounded, so answers and every pruning count equal those
+    of the plain lists, bit for bit; the database spans several buckets of each shape."""
+    _say(f"nn_search lbi_buckets n={n} w={w} N={N} p={p} k={k}")
+    X = walks(N, n, 38)
+    Ys = walks(11, n, 39)
+    db = L.Db(ctx, to_dev(X))
+    Yd = to_dev(Ys)
+    ri, rd, rst = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
+    L.lbimp_ctx_set_option(ctx, "lbi_buckets", 1)
+    try:
+        idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
+    finally:
+        L.lbimp_ctx_set_option(ctx, "lbi_buckets", 0)
+    assert torch.equal(idx, ri) and torch.equal(dist, rd)
+    assert np.array_equal(st[:, :5], rst[:, :5]) and np.array_equal(st[:, 6], rst[:, 6])
+    m = 3 if n <= 512 else 1
+    check_knn(X, Ys[:m], w, p, k, idx.cpu().numpy()[:m], dist.cpu().numpy()[:m], f"lbi_buckets n={n} w={w}")
+    db.close()
+
+
+@pytest.mark.parametrize("depth", [0])
+@pytest.mark.parametrize("n,w", [(128, 13), (256, 26), (200, 31), (300, 40)])
+def test_nn_search_lbi_pipeline_depth(L, ctx, depth, n, w):
+    """The register LB_Improved kernel with rows staged in batches instead of loaded a block
+    ahead (the default): identical answers and counts."""
+    _say(f"nn_search lbi_pipeline={depth} n={n} w={w}")
+    X = walks(4000, n, 40)
+    Ys = walks(9, n, 41)
+    db = L.Db(ctx, to_dev(X))
+    Yd = to_dev(Ys)
+    ri, rd, rst = L.lbimp_nn_search(ctx, db, Yd, w, 1, 2, "improved")
+    L.lbimp_ctx_set_option(ctx, "lbi_pipeline", depth)
+    try:
+        idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, 1, 2, "improved")
+    finally:
+        L.lbimp_ctx_set_option(ctx, "lbi_pipeline", 1)
+    assert torch.equal(idx, ri) and torch.equal(dist, rd)
+    assert np.array_equal(st[:, :5], rst[:, :5])
+    check_knn(X, Ys[:2], w, 1, 2, idx.cpu().numpy()[:2], dist.cpu().numpy()[:2], f"lbi_pipeline={depth}")
+    db.close()
+
+
 @pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
 @pytest.mark.parametrize("p,k", [(1, 1), (2, 5), (INF, 3)])
 @pytest.mark.parametrize("pd", [0, 1])
