@@ -1325,10 +1325,7 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
         mix((uint64_t)specs[g].Q);
         mix((uint64_t)specs[g].w);
         mix((uint64_t)(specs[g].k * 2 + (plan.mixed_k[g] ? 1 : 0)));
-        const Knobs &kn = specs[g].kn;
-        mix((uint64_t)(kn.seeds * 1000000 + kn.sweep_shape * 10000 + kn.lbi_pipeline * 1000 + kn.dtw_group * 100 +
-                       kn.seed_lane * 10 + kn.cascade + (kn.pd ? 100000000 : 0) + (kn.lbi_abandon ? 200000000 : 0) +
-                       (kn.lbi_buckets ? 400000000 : 0)));
+        for (int v : knob_values(specs[g].kn)) mix((uint64_t)(uint32_t)v);
     }
     if (!ctx->use_graph && width <= 1) {
         if (int r = enqueue_all(ctx->stream)) return r;
