@@ -101,6 +101,28 @@ class Scheduler:
         return None
 
 
+def pretune_ragged(L, ctx, dbs, queries, db_of, w, p: int = 1, k=1, mode: str = "improved"):
+    """Autotune every group of a ragged batch on its own before the batch runs.
+
+    The library runs a ragged batch as one search per (database, effective band) group, each
+    with the tuned choices recorded for its shape.  This tunes each group as a homogeneous
+    batch (``lbimp_autotune`` on the group's queries, with the group's largest k), so the ragged
+    call then uses the tuned choices without tuning inside it.  ``queries`` is a list of host
+    float32 series."""
+    import torch
+    kq = np.broadcast_to(np.asarray(k, dtype=np.int64), (len(queries),))
+    wq = np.broadcast_to(np.asarray(w, dtype=np.int64), (len(queries),))
+    groups = {}
+    for q, (b, wv) in enumerate(zip(db_of, wq)):
+        n = len(queries[q])
+        groups.setdefault((int(b), min(int(wv), n - 1)), []).append(q)
+    for (b, wb), ids in sorted(groups.items()):
+        Y = torch.from_numpy(np.stack([np.asarray(queries[q], np.float32) for q in ids])).cuda()
+        L.lbimp_autotune(ctx, dbs[b], Y, wb, p, int(kq[ids].max()), mode)
+    torch.cuda.synchronize()
+    return len(groups)
+
+
 def latency_summary(results) -> dict:
     lat = np.array([r.latency for r in results], dtype=np.float64) * 1e3
     if lat.size == 0:

@@ -184,16 +184,18 @@ def test_ragged_invalid_arguments(L, ctx, dbs):
 def test_ragged_uneven4096_full_size(L):
     """The uneven batch the benchmark times -- 4,096 random-walk queries, n uniform over
     {64, 128, 256, 512, 1024}, w = round(f n) with f in {0.05, 0.1, 0.2}, 20,000 series per
-    length, p = 1, 1-NN -- in its launch configuration (graph replay on four streams, the
-    context's default choices): every query equals the search of its group alone, bit for bit, and the first query
+    length, p = 1, 1-NN -- in its launch configuration (every group autotuned on its own before
+    the batch, graph replay on four streams): every query equals the search of its group alone, bit for bit, and the first query
     of every (length, band) group matches the oracle."""
     _say("ragged uneven batch, full size (4096 queries, 5 x 20000 series)")
+    from paper_0811_3301_amd.serve import pretune_ragged
     ctx2 = L.Ctx(0)
     dbs64, qs, db_of, w = gen.make_ragged_workload()
     Xs = [f32(d) for d in dbs64]
     del dbs64
     handles = [L.Db(ctx2, to_dev(X)) for X in Xs]
     try:
+        assert pretune_ragged(L, ctx2, handles, [f32(q) for q in qs], db_of, w, 1, 1, "improved") == 15
         offsets = np.zeros(len(qs) + 1, np.int64)
         offsets[1:] = np.cumsum([len(y) for y in qs])
         packed = to_dev(f32(np.concatenate(qs)))
