@@ -230,7 +230,12 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t) {
 }
 hipError_t hipEventQuery(hipEvent_t e) {
     if (!e) die("query of a null event");
-    return hipSuccess;
+    // work is sometimes still pending on a real device: report it now and then, so that the
+    // callers' paths for an unfinished upload (a new staging buffer, a wait) run too
+    rng ^= rng << 13;
+    rng ^= rng >> 7;
+    rng ^= rng << 17;
+    return rng % 3 == 0 ? hipErrorNotReady : hipSuccess;
 }
 hipError_t hipEventSynchronize(hipEvent_t e) {
     if (!e) die("synchronisation on a null event");
