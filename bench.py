@@ -400,6 +400,27 @@ def lbi_abandon_bench(L, steps=10):
     return out
 
 
+def strip_bench(L, steps=3, N=5_000, Q=16):
+    """The wide-band DTW kernels on their own: brute-force search (every pair's full DTW) of Q
+    random-walk queries over N x 1024 random walks at w = 102 and 205, p = 1, untuned (lane per
+    pair in strips of rows).  Reports DTW cells per second: n (2w + 1) - w (w + 1) per pair."""
+    import torch
+    from paper_0811_3301_amd import gen
+    n = 1024
+    ctx = L.Ctx(0)
+    db = L.Db(ctx, torch.from_numpy(gen.random_walk(N, n, gen.rng(4, gen.ROLE_DB, 5)).astype(np.float32)).cuda())
+    Yd = torch.from_numpy(gen.random_walk(Q, n, gen.rng(4, gen.ROLE_QUERY, 10)).astype(np.float32)).cuda()
+    out = {}
+    for w in (102, 205):
+        t = time_mode(L, ctx, db, Yd, w, 1, "brute", steps, 1)
+        cells = Q * N * (n * (2 * w + 1) - w * (w + 1))
+        out[f"w{w}"] = dict(ms_per_call=t["ms_per_step"], cells_per_s=cells / (t["ms_per_step"] / 1e3),
+                            frac_of_alu_peak=DTW_INSTR_PER_CELL * cells / (t["ms_per_step"] / 1e3) / VALU_PEAK)
+    db.close()
+    ctx.close()
+    return dict(workload=f"brute-force DTW_1, {Q} queries over {N} x {n} random walks", **out)
+
+
 def triangle_bench(L, ctx, count=100_000, n=100, steps=5):
     """App. B: 100,000 triples (x, y, z) of 100-sample random walks (and white noise),
     unconstrained DTW_1 and DTW_2 (w = n), C = DTW(x,z) / (DTW(x,y) + DTW(y,z)); one
@@ -510,7 +531,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy (calibrates the PMC byte counters)")
     ap.add_argument("--only", choices=("ragged", "serving", "shapes", "triangle", "lbsingle", "pd", "abandon",
-                                       "batch1m"),
+                                       "batch1m", "strip"),
                     help="run only the uneven-batch or the serving measurement and print its JSON (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -551,6 +572,9 @@ def main():
         print(json.dumps({"batch1m_stage_ms": st}), flush=True)
         big.close()
         ctx.close()
+        return
+    if args.only == "strip":
+        print(json.dumps(strip_bench(L, args.steps)), flush=True)
         return
     if args.only == "abandon":
         print(json.dumps(lbi_abandon_bench(L, args.steps)), flush=True)
@@ -657,10 +681,12 @@ def main():
         log("serving loop")
         serving = serving_bench(L, rates=(1_000, 2_000, 5_000, 10_000, 20_000, 35_000, 50_000))
 
-    lbi_ab = None
+    lbi_ab = wide = None
     if not args.quick:
         log("early abandoning inside LB_Improved, off and on")
         lbi_ab = lbi_abandon_bench(L)
+        log("wide-band DTW (brute force, n=1024, w=102 and 205)")
+        wide = strip_bench(L)
 
     triangle = None
     if not (args.quick or args.no_triangle):
@@ -710,6 +736,7 @@ def main():
         "serving": serving,
         "triangle": triangle,
         "lbi_abandon": lbi_ab,
+        "wide_band_dtw": wide,
     }
     print(json.dumps(out), flush=True)
     db.close()
