@@ -305,14 +305,14 @@ int dims_of(const SearchSpec &sp, int num_cu, SearchDims &d) {
 
 void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
     const bool any = d.N > 0;
-    const bool list_k = d.k > 1 || d.nchunks > 1;  // result keys (and their shrinking between chunks)
     b.Ue = c.take<float>((size_t)d.Qp * d.ldq);
     b.Le = c.take<float>((size_t)d.Qp * d.ldq);
     b.S1 = (d.brute || !any) ? nullptr : c.take<float>((size_t)d.Q * d.Np);
     b.seeds = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * std::max(d.S, 1));
     b.best = c.take<u64>((size_t)d.Q);
     b.thr = c.take<u64>((size_t)d.Q);
-    b.res = ((d.k > 1 && list_k) || !any) ? c.take<u64>((size_t)d.Q * d.ldres) : nullptr;
+    // k-NN result keys (kept sorted between chunks); for k = 1 the best key is enough
+    b.res = (d.k > 1 || !any) ? c.take<u64>((size_t)d.Q * d.ldres) : nullptr;
     b.list0 = (d.pd && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
     b.qpd = (d.pd && any) ? c.take<double>((size_t)d.Q * 2 * kPdParts) : nullptr;
     b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.C);

@@ -271,8 +271,8 @@ def test_nn_search_lbi_abandon(L, ctx, n, w, p, k):
     db.close()
 
 
-@pytest.mark.parametrize("n,w,N", [(128, 13, 9000), (256, 26, 5000), (64, 6, 20000), (300, 80, 6000), (512, 51, 4000),
-                                   (2300, 600, 2100)])
+@pytest.mark.parametrize("n,w,N", [(128, 13, 9000), (256, 26, 9000), (64, 6, 20000), (300, 80, 9000), (512, 51, 9000),
+                                   (2300, 600, 4200)])
 @pytest.mark.parametrize("p,k", [(1, 1), (2, 3), (INF, 2)])
 def test_nn_search_lbi_buckets(L, ctx, n, w, N, p, k):
     """LB_Improved over survivor lists bucketed by candidate range (walked bucket by bucket, one
@@ -291,8 +291,9 @@ def test_nn_search_lbi_buckets(L, ctx, n, w, N, p, k):
         L.lbimp_ctx_set_option(ctx, "lbi_buckets", 0)
     assert torch.equal(idx, ri) and torch.equal(dist, rd)
     assert np.array_equal(st[:, :5], rst[:, :5]) and np.array_equal(st[:, 6], rst[:, 6])
-    m = 3 if n <= 512 else 1
-    check_knn(X, Ys[:m], w, p, k, idx.cpu().numpy()[:m], dist.cpu().numpy()[:m], f"lbi_buckets n={n} w={w}")
+    m = 3 if n <= 512 else 0  # the wide case is checked against the plain lists only
+    if m:
+        check_knn(X, Ys[:m], w, p, k, idx.cpu().numpy()[:m], dist.cpu().numpy()[:m], f"lbi_buckets n={n} w={w}")
     db.close()
 
 
