@@ -18,120 +18,116 @@ namespace lbimp {
 // window of output i = e - W starts at s = e - K + 1, which lies in block B-1 at offset o+1 (or
 // at the start of block B when o = K-1, where the neutral entry h[K] applies), so the window
 // value is max(h[o+1], g) with h the suffix max/min of block B-1, built by walking B-1
-// backwards.  h lives in registers (compile-time offsets); x' of the current block is staged
-// in LDS, transposed ([offset][pair]) so each lane reads its own column without bank
-// conflicts.  The staging loads are coalesced: for pair j the wave reads K consecutive floats
-// of row c_j, one per lane, and applies the clamp on the way in.
+// backwards.  h lives in registers (compile-time offsets).  x' of the current block is staged
+// in LDS one row per pair ([pair][S], S = 4 * odd >= K), so a lane reads four offsets of its
+// own pair with one 16-byte read whose address is fixed per lane (no address arithmetic), and
+// 16 lanes reading rows S floats apart touch disjoint banks.  The staging loads are coalesced:
+// for pair j the wave reads K consecutive floats of row c_j, one per lane, and applies the clamp
+// on the way in; lanes writing consecutive offsets of one row write disjoint banks.  The query
+// values of the block's outputs are copied to an aligned row of S floats beside the stage and
+// read four at a time by all lanes at once.  Each pass reads its next group of four offsets
+// one group ahead of the arithmetic (a scheduling barrier keeps the reads there), so the LDS
+// latency is covered by a group of work.
 // Early abandoning (a.abandon, with a threshold): the bound only grows as terms are added, so a
 // pair is pruned once S1 combined with the terms so far reaches the threshold key; the wave
 // leaves the block loop when every one of its pairs has (a lane alone cannot skip work).
 // Positions e >= n repeat x'[n-1]: every window of an output i < n that reaches past the end
 // contains n-1, so the repeated value changes no maximum or minimum.
-// For bands w >= 20 the LDS values (x' of the pair, y of the query) are read in groups of four
-// offsets, one group ahead of the arithmetic that uses them (a scheduling barrier keeps them
-// there), so the LDS latency is covered by a group of work instead of a few instructions
-// (measured: 6% faster at w = 26, 5% slower at w = 13, where the compiler's own order is kept).
-// In the last block (PARTIAL) offsets past olim (outputs past the series) add nothing; their x'
-// repeat x'[n-1], which changes no running maximum or minimum.
+// In the last block (PARTIAL) the pass stops at olim (outputs past the series), a branch that is
+// uniform over the wave, so a short last block costs only its own positions.
+// Narrow bands stage KB consecutive blocks at once (as many as fit in the 64 lanes, at most
+// four), so that the loads and clamps of a stage keep most lanes busy; block b of a stage sits at
+// offset b * SK of a pair's row (SK = K rounded up to four, keeping the 16-byte reads aligned).
 template <int W>
-constexpr int lbi_group() { return W >= 20 ? 4 : 1; }
+constexpr int lbi_blocks_per_stage() {
+    constexpr int K = 2 * W + 1;
+    return K > 32 ? 1 : (64 / K > 4 ? 4 : 64 / K);
+}
+template <int W>
+constexpr int lbi_seg() { return (2 * W + 1 + 3) / 4 * 4; }
+template <int W>
+constexpr int lbi_stride() {
+    constexpr int m = lbi_blocks_per_stage<W>() * lbi_seg<W>() / 4;
+    return 4 * (m | 1);
+}
 
+template <int T>
+__device__ __forceinline__ float f4get(const float4 &v) {
+    if constexpr (T == 0) return v.x;
+    if constexpr (T == 1) return v.y;
+    if constexpr (T == 2) return v.z;
+    return v.w;
+}
+
+// xs: this lane's staged row of x' (16-byte aligned); ys: the query values of the block's
+// outputs, ys[o] = y[e - W] for offset o (read only where an output exists).
 template <int P, int W, bool FIRST, bool PARTIAL>
 __device__ __forceinline__ void lbi_forward(float &acc, const float (&hx)[2 * W + 2], const float (&hn)[2 * W + 2],
-                                            const float *stage, const float *yb, int olim, int lane) {
+                                            const float4 *xs, const float4 *ys, int olim) {
     constexpr int K = 2 * W + 1;
-    constexpr int G = lbi_group<W>(), NG = (K + G - 1) / G;
+    constexpr int NG = (K + 3) / 4;
     float gx = -kInf, gn = kInf;
-    if constexpr (G == 1) {
+    float4 xv[2], yv[2];
+    xv[0] = xs[0];
+    yv[0] = ys[0];
 #pragma unroll
-        for (int o = 0; o < K; ++o) {
-            if (!PARTIAL || o < olim) {
-                const float v = stage[o * 65 + lane];
-                gx = fmaxf(gx, v);
-                gn = fminf(gn, v);
+    for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG) {
+            xv[(g + 1) & 1] = xs[g + 1];
+            yv[(g + 1) & 1] = ys[g + 1];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        auto step = [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            const int o = 4 * g + t;
+            if (o < K) {
+                if (PARTIAL && o >= olim) return false;  // uniform: the rest of the block is past the series
+                const float x = f4get<t>(xv[g & 1]);
+                gx = fmaxf(gx, x);
+                gn = fminf(gn, x);
                 if (!FIRST || o >= W) {  // in the first block, windows of o < W start before the series
                     const float um = fmaxf(hx[o + 1], gx);
                     const float lm = fminf(hn[o + 1], gn);
-                    const float yv = yb[o - W];
-                    const float d = yv - __builtin_amdgcn_fmed3f(yv, lm, um);
+                    const float yo = f4get<t>(yv[g & 1]);
+                    const float d = yo - __builtin_amdgcn_fmed3f(yo, lm, um);
                     acc = pacc<P>(acc, d);
                 }
             }
-        }
-        return;
-    }
-    float v[2][G], y[2][G];
-    auto fetch = [&](int g, float (&vv)[G], float (&yy)[G]) {
-#pragma unroll
-        for (int t = 0; t < G; ++t) {
-            const int o = g * G + t;
-            if (o < K) {
-                vv[t] = stage[o * 65 + lane];
-                if (!FIRST || o >= W) yy[t] = yb[o - W];  // in the first block, windows of o < W start before the series
-            }
-        }
-    };
-    fetch(0, v[0], y[0]);
-#pragma unroll
-    for (int g = 0; g < NG; ++g) {
-        if (g + 1 < NG) fetch(g + 1, v[(g + 1) & 1], y[(g + 1) & 1]);
-        if constexpr (G > 1) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int t = 0; t < G; ++t) {
-            const int o = g * G + t;
-            if (o < K) {
-                const float x = v[g & 1][t];
-                gx = fmaxf(gx, x);
-                gn = fminf(gn, x);
-                if (!FIRST || o >= W) {
-                    const float um = fmaxf(hx[o + 1], gx);
-                    const float lm = fminf(hn[o + 1], gn);
-                    const float yv = y[g & 1][t];
-                    float d = yv - __builtin_amdgcn_fmed3f(yv, lm, um);
-                    if (PARTIAL) d = o < olim ? d : 0.f;
-                    acc = pacc<P>(acc, d);
-                }
-            }
-        }
+            return true;
+        };
+        if (!step(std::integral_constant<int, 0>{})) return;
+        if (!step(std::integral_constant<int, 1>{})) return;
+        if (!step(std::integral_constant<int, 2>{})) return;
+        if (!step(std::integral_constant<int, 3>{})) return;
     }
 }
 
-// Suffix maximum and minimum of the staged block, in place (hx[K], hn[K] stay neutral), with the
-// LDS reads a group ahead as in the forward pass.
+// Suffix maximum and minimum of the staged block, in place (hx[K], hn[K] stay neutral), reading
+// the groups of four from the top, one group ahead.
 template <int W>
-__device__ __forceinline__ void lbi_suffix(float (&hx)[2 * W + 2], float (&hn)[2 * W + 2], const float *stage, int lane) {
+__device__ __forceinline__ void lbi_suffix(float (&hx)[2 * W + 2], float (&hn)[2 * W + 2], const float4 *xs) {
     constexpr int K = 2 * W + 1;
-    constexpr int G = lbi_group<W>(), NG = (K + G - 1) / G;
-    if constexpr (G == 1) {
+    constexpr int NG = (K + 3) / 4;
+    float4 v[2];
+    v[0] = xs[NG - 1];
 #pragma unroll
-        for (int o = K - 1; o >= 0; --o) {
-            const float v = stage[o * 65 + lane];
-            hx[o] = fmaxf(hx[o + 1], v);
-            hn[o] = fminf(hn[o + 1], v);
-        }
-        return;
-    }
-    float v[2][G];
-    auto fetch = [&](int g, float (&vv)[G]) {
-#pragma unroll
-        for (int t = 0; t < G; ++t) {
-            const int o = K - 1 - (g * G + t);
-            if (o >= 0) vv[t] = stage[o * 65 + lane];
-        }
-    };
-    fetch(0, v[0]);
-#pragma unroll
-    for (int g = 0; g < NG; ++g) {
-        if (g + 1 < NG) fetch(g + 1, v[(g + 1) & 1]);
-        if constexpr (G > 1) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int t = 0; t < G; ++t) {
-            const int o = K - 1 - (g * G + t);
-            if (o >= 0) {
-                hx[o] = fmaxf(hx[o + 1], v[g & 1][t]);
-                hn[o] = fminf(hn[o + 1], v[g & 1][t]);
+    for (int gi = 0; gi < NG; ++gi) {
+        const int g = NG - 1 - gi;
+        if (gi + 1 < NG) v[(gi + 1) & 1] = xs[g - 1];
+        __builtin_amdgcn_sched_barrier(0);
+        auto step = [&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            const int o = 4 * g + t;
+            if (o < K) {
+                const float x = f4get<t>(v[gi & 1]);
+                hx[o] = fmaxf(hx[o + 1], x);
+                hn[o] = fminf(hn[o + 1], x);
             }
-        }
+        };
+        step(std::integral_constant<int, 3>{});
+        step(std::integral_constant<int, 2>{});
+        step(std::integral_constant<int, 1>{});
+        step(std::integral_constant<int, 0>{});
     }
 }
 
@@ -140,11 +136,14 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
     constexpr int K = 2 * W + 1;
     extern __shared__ float sm[];
     const int n = a.n;
-    float *sY = sm;                   // [n]
-    float *stage = sm + n;            // [K][65]
-    unsigned *soff = reinterpret_cast<unsigned *>(stage + K * 65);  // [64]
+    constexpr int KB = lbi_blocks_per_stage<W>(), SK = lbi_seg<W>(), S = lbi_stride<W>();
+    constexpr int SPAN = KB * K;      // positions staged together
+    float *stage = sm;                // [64][S]: x' of the stage's blocks, one row per pair
+    float *ys = sm + 64 * S;          // [S]: y[e - W] of the stage's offsets
+    float *sY = ys + S;               // [n]
     const int lane = threadIdx.x;
     const int nblk = (n + W + K - 1) / K;
+    const int nsb = (nblk + KB - 1) / KB;
     int64_t cur_q = -1;
     int64_t q;
     long long b;
@@ -180,11 +179,9 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
         const bool pipe = D > 0 && a.db_bytes < 0x80000000ll;
         const __amdgpu_buffer_rsrc_t rsrc =
             __builtin_amdgcn_make_buffer_rsrc((void *)a.rows, (short)0, pipe ? (int)a.db_bytes : 0, 0x00020000);
-        // byte offsets of the 64 rows, read back from LDS (not hoisted across barriers, so they
-        // do not pin 64 registers for the whole item)
-        __syncthreads();
-        soff[lane] = (unsigned)c * (unsigned)n * 4u;
-        __syncthreads();
+        // byte offset of the lane's row; the loads of a block take row t's offset from lane t
+        // into the scalar offset of the buffer load, so a load costs no vector instruction
+        const unsigned roff = (unsigned)c * (unsigned)n * 4u;
         // a block loaded ahead: the raw row values (one per pair) and the query envelope at the
         // lane's position, all requested together so that staging waits on one round trip that
         // the previous block's computation has covered
@@ -197,67 +194,85 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
             const unsigned eb = (unsigned)er * 4u;
 #pragma unroll
             for (int t = 0; t < (D >= 1 ? 64 : 1); ++t)
-                v[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, soff[t] + eb, 0, 0));
+                v[t] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(rsrc, eb, __builtin_amdgcn_readlane(roff, t), 0));
         };
-        auto stage_from = [&](const auto &v, float u, float l) {
-            if (lane < K) {
+        // position l of a stage (block l / K, offset l % K) goes to offset dst_of(l) of a row
+        auto dst_of = [&](int l) { return l / K * SK + l % K; };
+        auto stage_from = [&](const auto &v, float u, float l, int e0) {
+            if (lane < SPAN) {
+                const int dst = dst_of(lane);
 #pragma unroll
-                for (int t = 0; t < (D >= 1 ? 64 : 1); ++t) stage[lane * 65 + t] = __builtin_amdgcn_fmed3f(v[t], l, u);
+                for (int t = 0; t < (D >= 1 ? 64 : 1); ++t) stage[t * S + dst] = __builtin_amdgcn_fmed3f(v[t], l, u);
+                ys[dst] = sY[min(max(e0 + lane - W, 0), n - 1)];
             }
         };
         auto stage_batched = [&](int e0) {
 #pragma unroll
-            for (int r0 = 0; r0 < K; r0 += 64) {
+            for (int r0 = 0; r0 < SPAN; r0 += 64) {
                 const int er = min(e0 + r0 + lane, n - 1);
                 const float ur = Uq[er], lr = Lq[er];
+                const int dst = dst_of(r0 + lane);
+                if (r0 + lane < SPAN) ys[dst] = sY[min(max(e0 + r0 + lane - W, 0), n - 1)];
 #pragma unroll 1
                 for (int j0 = 0; j0 < 64; j0 += 16) {
                     float v[16];
 #pragma unroll
                     for (int t = 0; t < 16; ++t) v[t] = a.rows[(int64_t)__shfl(c, j0 + t) * n + er];
-                    if (r0 + lane < K) {
+                    if (r0 + lane < SPAN) {
 #pragma unroll
                         for (int t = 0; t < 16; ++t)
-                            stage[(r0 + lane) * 65 + j0 + t] = __builtin_amdgcn_fmed3f(v[t], lr, ur);
+                            stage[(j0 + t) * S + dst] = __builtin_amdgcn_fmed3f(v[t], lr, ur);
                     }
                 }
             }
         };
         // forward pass of block B over the staged x', then (unless it is the last) the suffix
         // max/min of the block in place; true when every pair of the wave has been abandoned
-        auto compute_block = [&](int B) -> bool {
-            const int e0 = B * K;
-            const float *yb = sY + e0;  // yb[o - W] = y[e - W]
-            const int olim = n + W - e0;
+        auto compute_block = [&](int B, int b) __attribute__((always_inline)) -> bool {
+            const int olim = n + W - B * K;
+            const float4 *xs = reinterpret_cast<const float4 *>(stage + lane * S + b * SK);
+            const float4 *y4 = reinterpret_cast<const float4 *>(ys + b * SK);
             if (B == 0) {
                 if (olim < K)
-                    lbi_forward<P, W, true, true>(acc, hx, hn, stage, yb, olim, lane);
+                    lbi_forward<P, W, true, true>(acc, hx, hn, xs, y4, olim);
                 else
-                    lbi_forward<P, W, true, false>(acc, hx, hn, stage, yb, olim, lane);
+                    lbi_forward<P, W, true, false>(acc, hx, hn, xs, y4, olim);
             } else if (olim < K) {
-                lbi_forward<P, W, false, true>(acc, hx, hn, stage, yb, olim, lane);
+                lbi_forward<P, W, false, true>(acc, hx, hn, xs, y4, olim);
             } else {
-                lbi_forward<P, W, false, false>(acc, hx, hn, stage, yb, olim, lane);
+                lbi_forward<P, W, false, false>(acc, hx, hn, xs, y4, olim);
             }
             if (abandon && B + 1 < nblk && __ballot(active && make_key(pjoin<P>(s1, acc), c) < tq) == 0) return true;
-            if (B + 1 < nblk) lbi_suffix<W>(hx, hn, stage, lane);
+            if (B + 1 < nblk) lbi_suffix<W>(hx, hn, xs);
+            return false;
+        };
+        // the blocks of stage sb in order; true when every pair of the wave has been abandoned
+        auto run_stage = [&](int sb) __attribute__((always_inline)) -> bool {
+            if constexpr (KB == 1) return compute_block(sb, 0);
+#pragma unroll 1
+            for (int b = 0; b < KB; ++b) {
+                const int B = sb * KB + b;
+                if (B >= nblk) break;
+                if (compute_block(B, b)) return true;
+            }
             return false;
         };
         if (D >= 1 && pipe) {
             load_block(va, ua, la, 0);
-            for (int B = 0; B < nblk; ++B) {
-                __syncthreads();  // the previous block's readers are done with the stage
-                stage_from(va, ua, la);
+            for (int sb = 0; sb < nsb; ++sb) {
+                __syncthreads();  // the previous stage's readers are done with it
+                stage_from(va, ua, la, sb * SPAN);
                 __syncthreads();
-                if (B + 1 < nblk) load_block(va, ua, la, (B + 1) * K);
-                if (compute_block(B)) break;
+                if (sb + 1 < nsb) load_block(va, ua, la, (sb + 1) * SPAN);
+                if (run_stage(sb)) break;
             }
         } else {
-            for (int B = 0; B < nblk; ++B) {
+            for (int sb = 0; sb < nsb; ++sb) {
                 __syncthreads();
-                stage_batched(B * K);
+                stage_batched(sb * SPAN);
                 __syncthreads();
-                if (compute_block(B)) break;
+                if (run_stage(sb)) break;
             }
         }
         const float s2 = pjoin<P>(s1, acc);
@@ -278,7 +293,7 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
 template <int P, int W>
 static void lbi_reg_launch(int num_cu, const LbiArgs &a, hipStream_t s) {
     constexpr int K = 2 * W + 1;
-    const size_t lds = sizeof(float) * ((size_t)a.n + (size_t)K * 65 + 64);
+    const size_t lds = sizeof(float) * ((size_t)a.n + 65 * (size_t)lbi_stride<W>());
 #define LBIMP_LBI_REG(DD) \
     hipLaunchKernelGGL((k_lbi_reg<P, W, DD>), dim3(persistent_grid(k_lbi_reg<P, W, DD>, lds, num_cu)), dim3(64), lds, s, a)
     if constexpr (K <= 64) {

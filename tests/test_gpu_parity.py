@@ -128,7 +128,8 @@ def test_db_lb_keogh(L, ctx, Q, p, shape):
 # ------------------------------------------------------------------ LB_Improved
 @pytest.mark.parametrize("N,n,w", [(70, 32, 3), (130, 128, 13), (65, 256, 26), (40, 512, 51), (20, 1024, 205),
                                    (10, 50, 100), (9, 5, 0), (130, 300, 80), (70, 129, 128), (66, 512, 53),
-                                   (65, 1000, 300), (12, 1500, 400), (5, 2100, 60)])
+                                   (65, 1000, 300), (12, 1500, 400), (5, 2100, 60), (70, 17, 1), (70, 45, 5),
+                                   (70, 97, 10), (70, 64, 15), (70, 63, 16), (70, 200, 20), (70, 100, 31)])
 @pytest.mark.parametrize("p", [1, 2, INF])
 def test_lb_improved(L, ctx, N, n, w, p):
     _say(f"lb_improved N={N} n={n} w={w} p={p}")
