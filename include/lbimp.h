@@ -104,11 +104,19 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *                   groups; 0 or 1 runs them one after another on the context's stream (with
  *                   "graph" 0 no other stream is touched, which suits callers that already
  *                   overlap several contexts);
- *   "pd_prefilter"  0/1 (default 0): the searches start with pass 0, the piecewise-sum bound of
- *                   Sec. 9 (d = 8 part sums per series, 64 bytes per candidate), seed the
- *                   threshold from its smallest values, and compute LB_Keogh only of the
+ *   "pd_prefilter"  0..2 (default 0): the searches start with pass 0, the piecewise-sum bound of
+ *                   Sec. 9, and seed the threshold from its smallest values.  1: d = 8 part
+ *                   sums per series (fp64, 64 bytes per candidate), then LB_Keogh of the
  *                   candidates it keeps, reading their rows; it pays where the first pass is
- *                   bound by database reads (a few queries per database sweep);
+ *                   bound by database reads (a few queries per database sweep).  2: d = 32 part
+ *                   sums (fp32 with rounding margins that keep the bound below the exact one,
+ *                   128 bytes per candidate; series of at least 64 samples), in place of the
+ *                   LB_Keogh sweep: its survivors go straight to LB_Improved, which computes
+ *                   LB_Keogh from the same read of each row (two-pass search with w <= 52;
+ *                   otherwise 1 applies); it pays on smooth series, where sums over short parts
+ *                   prune almost as well as LB_Keogh;
+ *   "pd_fine"       0/1 (default 0): lbimp_db_pd_bound evaluates the d = 32 cover of
+ *                   "pd_prefilter" 2 instead of d = 8 (LBIMP_E_UNSUPPORTED for n < 64);
  *   "workspace_limit" bytes (default 0, no bound): a search whose workspace would exceed it
  *                   splits the database into chunks of candidates (multiples of 2,048) searched
  *                   one after another, each through the whole path, the threshold carried from
@@ -132,8 +140,8 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value);
  * `max` stage durations in milliseconds to host array `ms` (order: envelope, lb_keogh
  * sweep, seed selection, seed DTW, compaction, lb_improved, dtw, finalize); it returns
  * the number of stages written, or a negative status.  With "pd_prefilter" the second
- * stage is the pass-0 scan and the compaction stage holds the pass-0 compaction and the
- * LB_Keogh of its survivors. */
+ * stage is the pass-0 scan and the compaction stage holds the pass-0 compaction and (1) the
+ * LB_Keogh of its survivors; with 2 the lb_improved stage computes LB_Keogh as well. */
 int lbimp_ctx_set_timing(lbimp_ctx *ctx, int enable);
 int lbimp_ctx_stage_times(lbimp_ctx *ctx, float *ms, int max);
 
@@ -168,7 +176,9 @@ int lbimp_db_lb_keogh(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const 
  * sums of v, lb[q][c] = sum_j d(P(x_c)_j, [P(L)_j, P(U)_j]) for p = 1 (the paper's bound of
  * LB_Keogh_1); for p = 2 the root of sum_j d_j^2 / |C_j|, for p = infinity max_j d_j / |C_j|
  * (power-mean inequality; both stay below LB_Keogh_p).  Sums in fp64, the bound rounded down
- * to float32.  U, L device [Q][n]; lb device [Q][N]. */
+ * to float32.  With the context option "pd_fine" the cover has 32 parts (m = floor(n/32)) and
+ * the bound is evaluated in fp32 with rounding margins that keep it below the exact one
+ * (LBIMP_E_UNSUPPORTED for n < 64).  U, L device [Q][n]; lb device [Q][N]. */
 int lbimp_db_pd_bound(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const float *L, int64_t Q, int32_t p,
                       float *lb);
 

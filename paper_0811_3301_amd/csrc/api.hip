@@ -112,7 +112,8 @@ struct lbimp_ctx {
     int sweep_shape = 0;           // option "sweep_shape"
     bool use_graph = true;         // option "graph" (lbimp_nn_search_ragged)
     int ragged_streams = kPoolStreams;  // option "ragged_streams"
-    bool pd_prefilter = false;          // option "pd_prefilter"
+    int pd_prefilter = 0;               // option "pd_prefilter" (0, 1 or 2)
+    bool pd_fine_bound = false;         // option "pd_fine": lbimp_db_pd_bound on the 32-part cover
     bool lbi_abandon = false;           // option "lbi_abandon"
     bool lbi_buckets = false;           // option "lbi_buckets"
     size_t ws_limit = 0;                // option "workspace_limit" (bytes, 0: none)
@@ -137,6 +138,7 @@ struct lbimp_db {
     float *rows = nullptr;  // [N][n] row-major copy (gathers of the second pass and the DTW)
     float4 *il = nullptr;   // interleaved tiles for the LB_Keogh sweep
     double *pd = nullptr;   // [N][kPdParts] piecewise sums (Sec. 9) of the pass-0 scan
+    float4 *pdf = nullptr;  // sums over the 32-part cover, interleaved by 64-candidate tile (n >= kPdfMinN)
 };
 
 static int persistent_grid(const lbimp_ctx *ctx) { return std::max(1, ctx->num_cu); }  // CUs; kernels size by occupancy
@@ -208,7 +210,8 @@ struct Knobs {
     bool dtw_group;     // survivors' DTW with a group of lanes per pair (else a lane per pair)
     bool seed_lane;     // seeding DTWs with a lane per pair (else a group of lanes per pair)
     bool cascade;       // abandon on the row minimum plus the LB_Keogh terms still to come
-    bool pd = false;    // pass 0: piecewise-sum bound of every candidate, LB_Keogh only of its survivors
+    int pd = 0;         // pass 0: piecewise-sum bound of every candidate; 1: 8-part cover, LB_Keogh only of
+                        // its survivors; 2: 32-part cover, LB_Keogh inside the LB_Improved pass
     bool lbi_abandon = false;  // early abandoning inside the LB_Improved pass
     bool lbi_buckets = false;  // LB_Improved over bucketed survivor lists (XCD-local row reuse)
 };
@@ -235,6 +238,7 @@ struct SearchDims {
     int nb;              // buckets per chunk (1: the lists are not bucketed)
     size_t ring_bytes;  // strip-boundary scratch of the wide-band DTW
     bool brute, improved, from_minima, pd;
+    bool fine;           // pass 0 on the 32-part cover, then LB_Improved with LB_Keogh fused (pd = 2)
 };
 
 struct SearchBufs {
@@ -243,6 +247,7 @@ struct SearchBufs {
     u64 *best, *thr, *res, *wmin;
     long long *prefix, *tot;
     double *qpd;
+    float *qpf;
 };
 
 constexpr int64_t kChunkAlign = 2048;  // chunk sizes are multiples of the sweep's largest tile group
@@ -262,10 +267,16 @@ static void chunk_dims(const SearchSpec &sp, int64_t C, SearchDims &d) {
     // one bucket's rows stay in an XCD's L2 while the pairs of every query read them
     const int64_t span = compact_wave_span();
     d.bs = std::max<int64_t>(span, ((int64_t)(2 << 20) / (4 * (int64_t)d.n)) / span * span);
-    d.nb = (d.improved && sp.kn.lbi_buckets && d.C > d.bs) ? (int)((d.C + d.bs - 1) / d.bs) : 1;
+    d.nb = (d.improved && sp.kn.lbi_buckets && d.C > d.bs && !d.fine) ? (int)((d.C + d.bs - 1) / d.bs) : 1;
 }
 
 void layout(Carver &c, const SearchDims &d, SearchBufs &b);
+
+// pass 0 on the 32-part cover needs the database's fine sums and the register LB_Improved kernel
+// (which computes LB_Keogh itself in that flow)
+bool fine_supported(const lbimp_db *db, bool improved, int wb) {
+    return improved && db->pdf != nullptr && wb <= kLbiRegMaxW;
+}
 
 int dims_of(const SearchSpec &sp, int num_cu, SearchDims &d) {
     d.n = sp.db->n;
@@ -283,7 +294,8 @@ int dims_of(const SearchSpec &sp, int num_cu, SearchDims &d) {
     d.WL = d.improved ? lbi_batch(d.n, d.wb) : 1;
     if (d.improved && d.WL == 0)
         return fail(LBIMP_E_UNSUPPORTED, "LB_Improved state for n = %d, w = %d exceeds LDS", d.n, d.wb);
-    d.pd = sp.kn.pd && !d.brute;
+    d.pd = sp.kn.pd != 0 && !d.brute;
+    d.fine = d.pd && sp.kn.pd == 2 && fine_supported(sp.db, d.improved, d.wb);  // else the 8-part cover
     d.ring_bytes = dtw_strip_scratch(d.p, d.n, d.wb, num_cu);
     chunk_dims(sp, d.N, d);
     if (sp.ws_limit && d.N > kChunkAlign) {
@@ -313,8 +325,9 @@ void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
     b.thr = c.take<u64>((size_t)d.Q);
     // k-NN result keys (kept sorted between chunks); for k = 1 the best key is enough
     b.res = (d.k > 1 || !any) ? c.take<u64>((size_t)d.Q * d.ldres) : nullptr;
-    b.list0 = (d.pd && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
-    b.qpd = (d.pd && any) ? c.take<double>((size_t)d.Q * 2 * kPdParts) : nullptr;
+    b.list0 = (d.pd && !d.fine && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
+    b.qpd = (d.pd && !d.fine && any) ? c.take<double>((size_t)d.Q * 2 * kPdParts) : nullptr;
+    b.qpf = (d.fine && any) ? c.take<float>((size_t)d.Q * kPdfQuery) : nullptr;
     b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.C);
     b.list2 = (d.improved && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
     b.counters = c.take<int>((size_t)d.Q * kCounters);  // cnt1, cnt2, rescnt, abandoned, cnt0 ([kCounters][Q])
@@ -391,7 +404,10 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
     stage(1);
     const bool chunked = d.nchunks > 1;
     if (chunked) HIPTRY(launch_fill_u64(reinterpret_cast<u64 *>(b.tot), 0, Q * 3, s));
-    if (d.pd) HIPTRY(launch_pd_query(b.Ue, b.Le, d.ldq, Q, n, b.qpd, s));
+    if (d.fine)
+        HIPTRY(launch_pdf_query(b.Ue, b.Le, d.ldq, Q, n, b.qpf, s));
+    else if (d.pd)
+        HIPTRY(launch_pd_query(b.Ue, b.Le, d.ldq, Q, n, b.qpd, s));
     // The candidates are searched in chunks [c0, c0 + cj), each through the whole path; the
     // threshold carries over (the best key for k = 1, the k best keys for k > 1), so every chunk
     // prunes at least as well as the first.  Candidate indices stay global: the chunk's
@@ -410,7 +426,12 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
                               b.ring, d.ring_bytes, nullptr, 0, s));
         } else {
             float *S1v = b.S1 - c0;  // S1v[q * Np + c] is candidate c of this chunk
-            if (d.pd) {
+            if (d.fine) {
+                // pass 0 on the 32-part cover, fp32, 128 bytes per candidate (the chunk starts at a
+                // multiple of 64 candidates, a tile of the interleaved sums)
+                HIPTRY(launch_pdf_scan(p, db->pdf + (c0 / 64) * (kPdFine / 4) * 64, cj, n, b.qpf, Q, b.S1, d.Np,
+                                       false, b.wmin, s, c0));
+            } else if (d.pd) {
                 // pass 0: the piecewise-sum bound (Sec. 9) of every candidate, 64 bytes per candidate
                 HIPTRY(launch_pd_scan(p, db->pd + c0 * kPdParts, cj, n, b.qpd, Q, b.S1, d.Np, false, false,
                                       b.wmin, s, c0));
@@ -435,32 +456,45 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
                               b.ring, d.ring_bytes, nullptr, 0, s));
             if (k > 1) HIPTRY(launch_kth_key(b.res, d.ldres, rescnt, Q, k, sp.kq, b.thr, s));
             stage_first(4);
-            if (d.pd) {
-                // the pass-0 survivors, then LB_Keogh of their rows (pass 1) over their S1 entries; the
-                // others keep their pass-0 bound, at or above the threshold
-                HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list0, d.C, cnt0, s, c0));
-                HIPTRY(launch_items_prefix(cnt0, 0, Q, lbk_gather_batch(), b.prefix, s));
-                HIPTRY(launch_lbk_gather(p, db->rows, n, qd, PairList{b.list0, d.C, cnt0, 0}, b.prefix, Q, grid, S1v,
-                                         d.Np, s));
-            }
-            if (d.nb > 1) {  // survivors bucketed by candidate range for the LB_Improved pass
-                HIPTRY(launch_fill_i32(b.cntb, 0, Q * d.nb, s));
-                HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt1, s, c0, d.bs, b.cntb));
-            } else {
-                HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt1, s, c0));
-            }
-            stage_first(5);
             PairList dl{b.list1, d.C, cnt1, 0};
-            if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
-                if (d.nb > 1) {
-                    dl = PairList{b.list1, d.C, b.cntb, 0, 0, d.nb, d.bs, Q};
-                    HIPTRY(launch_items_prefix(b.cntb, 0, Q * d.nb, d.WL, b.prefix, s));
-                } else {
-                    HIPTRY(launch_items_prefix(cnt1, 0, Q, d.WL, b.prefix, s));
-                }
-                HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, S1v, d.Np, b.prefix, Q, nullptr,
-                                  grid, T, b.list2, d.C, cnt2, nullptr, sp.kn.lbi_pipeline, sp.kn.lbi_abandon, s));
+            if (d.fine) {
+                // the pass-0 survivors go straight to LB_Improved, which computes their LB_Keogh
+                // (pass 1) from the same read of each row: cnt0 counts the pass-0 survivors, cnt1
+                // those whose LB_Keogh stays below the threshold, cnt2 those of LB_Improved
+                HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt0, s, c0));
+                stage_first(5);
+                HIPTRY(launch_items_prefix(cnt0, 0, Q, d.WL, b.prefix, s));
+                HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, PairList{b.list1, d.C, cnt0, 0}, S1v,
+                                  d.Np, b.prefix, Q, nullptr, grid, T, b.list2, d.C, cnt2, nullptr, 1, false, s,
+                                  true, cnt1, S1v));
                 dl = PairList{b.list2, d.C, cnt2, 0};
+            } else {
+                if (d.pd) {
+                    // the pass-0 survivors, then LB_Keogh of their rows (pass 1) over their S1 entries;
+                    // the others keep their pass-0 bound, at or above the threshold
+                    HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list0, d.C, cnt0, s, c0));
+                    HIPTRY(launch_items_prefix(cnt0, 0, Q, lbk_gather_batch(), b.prefix, s));
+                    HIPTRY(launch_lbk_gather(p, db->rows, n, qd, PairList{b.list0, d.C, cnt0, 0}, b.prefix, Q, grid,
+                                             S1v, d.Np, s));
+                }
+                if (d.nb > 1) {  // survivors bucketed by candidate range for the LB_Improved pass
+                    HIPTRY(launch_fill_i32(b.cntb, 0, Q * d.nb, s));
+                    HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt1, s, c0, d.bs, b.cntb));
+                } else {
+                    HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt1, s, c0));
+                }
+                stage_first(5);
+                if (d.improved) {  // pass 2: LB_Improved of the survivors (Algorithm 3)
+                    if (d.nb > 1) {
+                        dl = PairList{b.list1, d.C, b.cntb, 0, 0, d.nb, d.bs, Q};
+                        HIPTRY(launch_items_prefix(b.cntb, 0, Q * d.nb, d.WL, b.prefix, s));
+                    } else {
+                        HIPTRY(launch_items_prefix(cnt1, 0, Q, d.WL, b.prefix, s));
+                    }
+                    HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, dl, S1v, d.Np, b.prefix, Q, nullptr,
+                                      grid, T, b.list2, d.C, cnt2, nullptr, sp.kn.lbi_pipeline, sp.kn.lbi_abandon, s));
+                    dl = PairList{b.list2, d.C, cnt2, 0};
+                }
             }
             stage_first(6);
             const bool dtw_ll = sp.kn.dtw_group && (wb <= kLaneMaxW || dtw_wavereg_wide_supported(n, wb));
@@ -495,14 +529,14 @@ static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int
 }
 
 static Knobs knobs_of(const std::array<int, kTuneKnobs> &v) {
-    Knobs k{v[0], v[2], v[1], v[3] != 0, v[4] != 0, v[5] != 0, v[6] != 0, v[7] != 0};
+    Knobs k{v[0], v[2], v[1], v[3] != 0, v[4] != 0, v[5] != 0, v[6], v[7] != 0};
     k.lbi_buckets = v[8] != 0;
     return k;
 }
 
 static std::array<int, kTuneKnobs> knob_values(const Knobs &k) {
     return {k.seeds, k.sweep_shape, k.lbi_pipeline, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0,
-            k.cascade ? 1 : 0, k.pd ? 1 : 0, k.lbi_abandon ? 1 : 0, k.lbi_buckets ? 1 : 0};
+            k.cascade ? 1 : 0, k.pd, k.lbi_abandon ? 1 : 0, k.lbi_buckets ? 1 : 0};
 }
 
 // The tuned choice for this batch shape if there is one, else the context's options.
@@ -530,7 +564,7 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     size_t search_bytes = 0;
     for (int sd : seed_opts)
         for (int sh : shape_opts)
-            for (bool pdv : {false, true})
+            for (int pdv : {0, 1, 2})
                 for (bool bk : {false, true}) {
                     SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr,
                                   Knobs{sd, 1, sh, false, false, true, pdv}};
@@ -653,9 +687,24 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
         Knobs kn = best;
         kn.cascade = !kn.cascade;
         if (int r = consider(kn)) return r;
-        kn = best;
-        kn.pd = !kn.pd;  // pass 0 pays where the first pass is bound by database reads (few queries)
-        if (int r = consider(kn)) return r;
+        // pass 0 on the 8-part cover pays where the first pass is bound by database reads (few
+        // queries); on the 32-part cover where the series are smooth enough for it to prune
+        // almost as well as LB_Keogh.  A new first pass can move the best seed count.
+        const Knobs b2 = best;
+        for (int pv = 0; pv <= 2; ++pv) {
+            if (pv == 2 && !fine_supported(db, improved, wb)) continue;
+            kn = b2;
+            kn.pd = pv;
+            if (int r = consider(kn)) return r;
+        }
+        if (best.pd != b2.pd) {
+            const Knobs b3 = best;
+            for (int sd : seed_opts) {
+                kn = b3;
+                kn.seeds = sd;
+                if (int r = consider(kn)) return r;
+            }
+        }
     }
     ctx->tuned[tune_key(db, Q, wb, p, k, mode)] = knob_values(best);
     *out = best;
@@ -889,7 +938,10 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
             return fail(LBIMP_E_INVALID, "ragged_streams must be in [0, %d]", kPoolStreams);
         ctx->ragged_streams = (int)value;
     } else if (!strcmp(name, "pd_prefilter")) {
-        ctx->pd_prefilter = value != 0;
+        if (value < 0 || value > 2) return fail(LBIMP_E_INVALID, "pd_prefilter must be 0, 1 or 2");
+        ctx->pd_prefilter = (int)value;
+    } else if (!strcmp(name, "pd_fine")) {
+        ctx->pd_fine_bound = value != 0;
     } else if (!strcmp(name, "lbi_abandon")) {
         ctx->lbi_abandon = value != 0;
     } else if (!strcmp(name, "lbi_buckets")) {
@@ -936,8 +988,10 @@ int lbimp_db_create(lbimp_ctx *ctx, const float *rows, int64_t N, int32_t n, lbi
     size_t rbytes = sizeof(float) * (size_t)std::max<int64_t>(N, 1) * n;
     size_t ibytes = sizeof(float4) * (size_t)std::max<int64_t>(T, 1) * n4 * 64;
     size_t pbytes = sizeof(double) * (size_t)std::max<int64_t>(N, 1) * kPdParts;
+    const bool fine = n >= kPdfMinN && N > 0;
+    size_t fbytes = sizeof(float4) * (size_t)T * (kPdFine / 4) * 64;
     if (hipMalloc(&db->rows, rbytes) != hipSuccess || hipMalloc(&db->il, ibytes) != hipSuccess ||
-        hipMalloc(&db->pd, pbytes) != hipSuccess) {
+        hipMalloc(&db->pd, pbytes) != hipSuccess || (fine && hipMalloc(&db->pdf, fbytes) != hipSuccess)) {
         (void)hipGetLastError();
         lbimp_db_destroy(db);
         return fail(LBIMP_E_NOMEM, "database allocation failed");
@@ -947,6 +1001,7 @@ int lbimp_db_create(lbimp_ctx *ctx, const float *rows, int64_t N, int32_t n, lbi
                                       ctx->stream);
         if (e == hipSuccess) e = launch_pack(rows, N, n, db->il, ctx->stream);
         if (e == hipSuccess) e = launch_pd_rows(rows, N, n, db->pd, ctx->stream);
+        if (e == hipSuccess && fine) e = launch_pdf_rows(rows, N, n, db->pdf, ctx->stream);
         if (e != hipSuccess) {
             lbimp_db_destroy(db);
             return fail(LBIMP_E_DEVICE, "database upload: %s", hipGetErrorString(e));
@@ -963,6 +1018,7 @@ void lbimp_db_destroy(lbimp_db *db) {
     if (db->rows) (void)hipFree(db->rows);
     if (db->il) (void)hipFree(db->il);
     if (db->pd) (void)hipFree(db->pd);
+    if (db->pdf) (void)hipFree(db->pdf);
     delete db;
 }
 
@@ -1032,6 +1088,17 @@ int lbimp_db_pd_bound(lbimp_ctx *ctx, const lbimp_db *db, const float *U, const 
     if (int r = check_shape(Q, db->n, 0, p)) return r;
     if (Q == 0 || db->N == 0) return LBIMP_OK;
     if (!U || !L || !lb) return fail(LBIMP_E_INVALID, "null pointer");
+    if (ctx->pd_fine_bound) {  // the 32-part cover (fp32 with rounding margins)
+        if (!db->pdf) return fail(LBIMP_E_UNSUPPORTED, "no 32-part sums for series shorter than %d", kPdfMinN);
+        Carver cv{nullptr};
+        cv.take<float>((size_t)Q * kPdfQuery);
+        if (int r = reserve(ctx, cv.off)) return r;
+        Carver c2{static_cast<char *>(ctx->ws)};
+        float *qpf = c2.take<float>((size_t)Q * kPdfQuery);
+        HIPTRY(launch_pdf_query(U, L, db->n, Q, db->n, qpf, ctx->stream));
+        HIPTRY(launch_pdf_scan(p, db->pdf, db->N, db->n, qpf, Q, lb, db->N, true, nullptr, ctx->stream, 0));
+        return LBIMP_OK;
+    }
     Carver cv{nullptr};
     cv.take<double>((size_t)Q * 2 * kPdParts);
     if (int r = reserve(ctx, cv.off)) return r;

@@ -234,6 +234,9 @@ struct LbiArgs {
     float *out_root;
     int pipeline;   // blocks loaded ahead in the register kernel: 0 or 1 (more registers, fewer exposed latencies)
     bool abandon;   // early abandoning: stop once the partial bound reaches the threshold (thr set)
+    bool fused = false;     // register kernel only: LB_Keogh computed here (S1 not read), see k_lbi_reg
+    int *cntk = nullptr;    // fused: per query, pairs whose LB_Keogh is below the threshold
+    float *S1out = nullptr; // fused: LB_Keogh of each surviving pair, [q * ldS + c]
 };
 
 // Wave-per-pair LB_Improved for wide bands (n + w <= 2048, 2w + 1 larger than a lane's slice).

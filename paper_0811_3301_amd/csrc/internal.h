@@ -18,6 +18,9 @@ constexpr int kLaneMaxW = 63;                 // widest band (half-width) of the
 constexpr int kLbiRegMaxW = 52;               // widest band of the register-state LB_Improved
 constexpr int kCounters = 5;                  // per-query counters of a search: cnt1, cnt2, rescnt, abandoned, cnt0
 constexpr int kPdParts = 8;                   // parts d of the piecewise-sum cover (Sec. 9)
+constexpr int kPdFine = 32;                   // parts of the fine cover of the fp32 first pass
+constexpr int kPdfQuery = 3 * kPdFine + 4;    // floats per query of the fine cover's query table
+constexpr int kPdfMinN = 64;                  // shortest series with a fine-cover table
 
 // Launch wrappers.  Every pointer is device memory; all launches go to `s`.
 // Each returns hipSuccess or the launch error.
@@ -87,6 +90,16 @@ hipError_t launch_pd_scan(int p, const double *pd, int64_t N, int n, const doubl
                           int64_t ldo, bool pad_inf, bool root, unsigned long long *wmin, hipStream_t s,
                           int64_t cbase = 0);
 
+// The same bound on the fine cover (kPdFine parts, fp32, with rounding margins that keep it below
+// the exact bound): pdf [ceil(N/64)][kPdFine/4][64] float4 interleaved sums of a database's
+// rows; qpf [Q][kPdfQuery] the query envelopes' sums and margins.  The scan writes out[q][c] and
+// the per-wave minima wmin[q][v] (v < pd_scan_waves(N)) like launch_pd_scan; the fine table is
+// addressed by 64-candidate tiles, so a chunk's cbase must be a multiple of 64.
+hipError_t launch_pdf_rows(const float *rows, int64_t N, int n, float4 *pdf, hipStream_t s);
+hipError_t launch_pdf_query(const float *U, const float *L, int ldq, int64_t Q, int n, float *qpf, hipStream_t s);
+hipError_t launch_pdf_scan(int p, const float4 *pdf, int64_t N, int n, const float *qpf, int64_t Q, float *out,
+                           int64_t ldo, bool root, unsigned long long *wmin, hipStream_t s, int64_t cbase);
+
 // Pair list description for the persistent second-pass and DTW kernels.
 // Bucketed lists (nb > 1): the candidates of each query are split by index range into nb
 // buckets; bucket k of query q holds its pairs at list[q * ldl + k * bs + j] and counts them in
@@ -116,12 +129,15 @@ struct QueryData {
 // state of this (n, w) does not fit in LDS.  The kernels read prefix (launch_items_prefix
 // over pl.cnt) only when pl.cnt is set; a fixed count per query maps items arithmetically.
 // abandon: stop a pair's sum once it reaches the threshold (register and wave-per-pair kernels;
-// only with thr and without out_root).
+// only with thr and without out_root).  fused (w <= kLbiRegMaxW, with thr): S1 is not read; the
+// kernel computes each pair's LB_Keogh from its row, counts per query in cntk the pairs whose
+// LB_Keogh alone is below the threshold, and writes a survivor's LB_Keogh to S1out[q*ldS + c].
 int lbi_batch(int n, int w);
 hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, QueryData qd, PairList pl, const float *S1,
                       int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
-                      int pipeline, bool abandon, hipStream_t s);
+                      int pipeline, bool abandon, hipStream_t s, bool fused = false, int *cntk = nullptr,
+                      float *S1out = nullptr);
 
 // LB_Keogh^p of the pairs of pl (the pass-0 survivors), reading each candidate's row: S1[q][c]
 // receives the bound.  Items hold lbk_gather_batch() pairs; prefix is launch_items_prefix over

@@ -122,10 +122,14 @@ __global__ __launch_bounds__(64) void k_lbi(const float *__restrict__ rows, int 
 hipError_t launch_lbi(int p, const float *rows, int64_t db_bytes, int n, int w, QueryData qd, PairList pl, const float *S1,
                       int64_t ldS, const long long *prefix, int64_t Q, int *ctr, int num_cu,
                       const unsigned long long *thr, int *list2, int64_t ldl2, int *cnt2, float *out_root,
-                      int pipeline, bool abandon, hipStream_t s) {
+                      int pipeline, bool abandon, hipStream_t s, bool fused, int *cntk, float *S1out) {
+    if (fused && w > kLbiRegMaxW) return hipErrorInvalidValue;  // only the register kernel computes LB_Keogh itself
     if (w <= kLbiRegMaxW || lbi_wave_supported(n, w)) {
         LbiArgs a{rows, db_bytes, n, qd, pl, S1, ldS, prefix, Q, ctr, thr, list2, ldl2, cnt2, out_root, pipeline,
                   abandon};
+        a.fused = fused;
+        a.cntk = cntk;
+        a.S1out = S1out;
         if (w > kLbiRegMaxW) return launch_lbi_wave(p, w, num_cu, a, s);
         if (p == 1) return launch_lbi_reg_p1(w, num_cu, a, s);
         return p == 2 ? launch_lbi_reg_p2(w, num_cu, a, s) : launch_lbi_reg_pinf(w, num_cu, a, s);

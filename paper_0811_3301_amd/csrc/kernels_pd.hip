@@ -163,6 +163,189 @@ hipError_t launch_pd_scan(int p, const double *pd, int64_t N, int n, const doubl
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ pass 0 on the fine cover
+// The same bound on the cover of kPdFine = 32 parts (width floor(n/32), the last part taking the
+// rest), evaluated in fp32 as the first pass of a search: on smooth series the sums over short
+// parts lose little against LB_Keogh, at 32 terms per pair instead of n.  The sums are formed in
+// fp64 and rounded to nearest fp32, so each differs from the exact sum by at most u = 2^-24 of
+// its size; the distance of a part is 1-Lipschitz in its three sums, so it exceeds the exact one
+// by at most u (|P(x)_j| + |P(L)_j| + |P(U)_j|) plus the rounding of the subtraction.  Every part
+// gives up 4u of that sum (for p = 1 once for the whole series), and the total is shrunk by a
+// few units of rounding, so the result stays below the exact bound of Sec. 9 and hence below
+// LB_Keogh.
+__device__ __forceinline__ void pdf_part(int n, int j, int &a, int &b) {
+    const int m = n / kPdFine;
+    a = j * m;
+    b = j + 1 < kPdFine ? (j + 1) * m : n;
+}
+
+constexpr float kPdfEps = 4.f * 5.9604645e-8f;  // 4u
+
+// pdf: [ceil(N/64)][kPdFine/4][64] float4 -- candidate 64t + l, parts 4g..4g+3 at [t][g][l].
+// One thread per (tile, group, lane); padding candidates get zeros.
+__global__ __launch_bounds__(256) void k_pdf_rows(const float *__restrict__ rows, int64_t N, int n,
+                                                   float4 *__restrict__ pdf) {
+    constexpr int G = kPdFine / 4;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tiles = (N + 63) / 64;
+    if (t >= tiles * G * 64) return;
+    const int lane = (int)(t % 64), g = (int)((t / 64) % G);
+    const int64_t c = (t / (64 * G)) * 64 + lane;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (c < N) {
+        const float *x = rows + c * (int64_t)n;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int a, b;
+            pdf_part(n, 4 * g + r, a, b);
+            double sum = 0.0;
+            for (int i = a; i < b; ++i) sum += (double)x[i];
+            v[r] = (float)sum;
+        }
+    }
+    pdf[t] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+hipError_t launch_pdf_rows(const float *rows, int64_t N, int n, float4 *pdf, hipStream_t s) {
+    const int64_t total = (N + 63) / 64 * (kPdFine / 4) * 64;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pdf_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rows, N, n, pdf);
+    return hipGetLastError();
+}
+
+// qpf[q]: P(U) [kPdFine], P(L) [kPdFine], the margins e_j = 4u (|P(U)_j| + |P(L)_j|) [kPdFine],
+// then their total and padding (kPdfQuery floats).  One thread per (query, part).
+__global__ __launch_bounds__(64) void k_pdf_query(const float *__restrict__ U, const float *__restrict__ L, int ldq,
+                                                   int64_t Q, int n, float *__restrict__ qpf) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= Q * kPdFine) return;
+    const int64_t q = g / kPdFine;
+    const int j = (int)(g % kPdFine);
+    int a, b;
+    pdf_part(n, j, a, b);
+    double su = 0.0, sl = 0.0;
+    for (int i = a; i < b; ++i) {
+        su += (double)U[q * ldq + i];
+        sl += (double)L[q * ldq + i];
+    }
+    const float fu = (float)su, fl = (float)sl;
+    float *o = qpf + q * kPdfQuery;
+    o[j] = fu;
+    o[kPdFine + j] = fl;
+    const float e = kPdfEps * (fabsf(fu) + fabsf(fl));
+    o[2 * kPdFine + j] = e;
+    // the total of the margins, summed by lane order within the part's wave slice
+    float tot = e;
+#pragma unroll
+    for (int off = 1; off < kPdFine; off <<= 1) tot += __shfl_xor(tot, off, kPdFine);
+    if (j == 0) o[3 * kPdFine] = tot * (1.f + 64.f * 5.9604645e-8f);
+}
+
+hipError_t launch_pdf_query(const float *U, const float *L, int ldq, int64_t Q, int n, float *qpf, hipStream_t s) {
+    const int64_t total = Q * kPdFine;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pdf_query, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, s, U, L, ldq, Q, n, qpf);
+    return hipGetLastError();
+}
+
+// Lane = candidate, block = 4 waves of 64 candidates x up to QG queries (blockIdx.y), the query
+// sums in LDS read as broadcasts.  Writes out[q][c] (pow domain, or root form with ROOT) and,
+// per query and wave, the smallest (bound, index) key of the wave's candidates.
+template <int P, int QG, bool ROOT>
+__global__ __launch_bounds__(256) void k_pdf_scan(const float4 *__restrict__ pdf, int64_t N, int n,
+                                                   const float *__restrict__ qpf, int64_t Q, float *__restrict__ out,
+                                                   int64_t ldo, unsigned long long *__restrict__ wmin, int64_t ldw,
+                                                   int64_t cbase) {
+    constexpr int G = kPdFine / 4;
+    __shared__ float4 sq[QG][kPdfQuery / 4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t q0 = (int64_t)blockIdx.y * QG;
+    for (int t = threadIdx.x; t < QG * kPdfQuery / 4; t += 256) {
+        const int64_t q = q0 + t / (kPdfQuery / 4);
+        sq[t / (kPdfQuery / 4)][t % (kPdfQuery / 4)] =
+            q < Q ? reinterpret_cast<const float4 *>(qpf + q * kPdfQuery)[t % (kPdfQuery / 4)]
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t c = tile * 64 + lane;
+    const bool valid = c < N;
+    float x[kPdFine];
+    float sx = 0.f;  // sum of |P(x)_j|
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const float4 v = pdf[(tile * G + g) * 64 + lane];
+        x[4 * g] = v.x, x[4 * g + 1] = v.y, x[4 * g + 2] = v.z, x[4 * g + 3] = v.w;
+        sx += fabsf(v.x) + fabsf(v.y) + fabsf(v.z) + fabsf(v.w);
+    }
+    float inv[kPdFine];  // 1 / part size (an empty part has zero distance)
+#pragma unroll
+    for (int j = 0; j < kPdFine; ++j) {
+        int a, b;
+        pdf_part(n, j, a, b);
+        inv[j] = b > a ? 1.f / (float)(b - a) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int qq = 0; qq < QG; ++qq) {
+        const int64_t q = q0 + qq;
+        if (q >= Q) break;
+        const float *sqf = reinterpret_cast<const float *>(sq[qq]);
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < kPdFine; ++j) {
+            const float d = x[j] - __builtin_amdgcn_fmed3f(x[j], sqf[kPdFine + j], sqf[j]);
+            if constexpr (P == 1) {
+                acc += fabsf(d);
+            } else {
+                // this part's margin: 4u (|P(x)_j| + |P(U)_j| + |P(L)_j|)
+                const float ds = fmaxf(fabsf(d) - fmaf(kPdfEps, fabsf(x[j]), sqf[2 * kPdFine + j]), 0.f);
+                if constexpr (P == 2)
+                    acc = fmaf(ds * inv[j], ds, acc);
+                else
+                    acc = fmaxf(acc, ds * inv[j]);
+            }
+        }
+        float f;
+        if constexpr (P == 1)
+            f = fmaxf(fmaf(acc, -64.f * 5.9604645e-8f, acc) - fmaf(kPdfEps, sx, sqf[3 * kPdFine]), 0.f);
+        else
+            f = acc * (1.f - 64.f * 5.9604645e-8f);
+        if (ROOT && P == 2) f = sqrtf(f) * (1.f - 4.f * 5.9604645e-8f);
+        if (valid) out[q * ldo + c] = f;
+        if (wmin) {
+            // the wave's smallest bound, then its lowest lane (the smallest index among equals)
+            float m = valid ? f : kInf;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
+            const unsigned long long ball = __ballot(valid && f == m);
+            if (lane == 0)
+                wmin[q * ldw + tile] = ball ? make_key(m, (int)(tile * 64 + __ffsll(ball) - 1 + cbase)) : kNoKey;
+        }
+    }
+}
+
+template <int P, bool ROOT>
+static void pdf_scan_launch(const float4 *pdf, int64_t N, int n, const float *qpf, int64_t Q, float *out, int64_t ldo,
+                            unsigned long long *wmin, int64_t cbase, hipStream_t s) {
+    constexpr int QG = 16;
+    const dim3 grid((unsigned)((N + 255) / 256), (unsigned)((Q + QG - 1) / QG));
+    hipLaunchKernelGGL((k_pdf_scan<P, QG, ROOT>), grid, dim3(256), 0, s, pdf, N, n, qpf, Q, out, ldo, wmin,
+                       pd_scan_waves(N), cbase);
+}
+
+hipError_t launch_pdf_scan(int p, const float4 *pdf, int64_t N, int n, const float *qpf, int64_t Q, float *out,
+                           int64_t ldo, bool root, unsigned long long *wmin, hipStream_t s, int64_t cbase) {
+    if (N == 0 || Q == 0) return hipSuccess;
+    if (p == 1)
+        pdf_scan_launch<1, false>(pdf, N, n, qpf, Q, out, ldo, wmin, cbase, s);
+    else if (p == 2)
+        root ? pdf_scan_launch<2, true>(pdf, N, n, qpf, Q, out, ldo, wmin, cbase, s)
+             : pdf_scan_launch<2, false>(pdf, N, n, qpf, Q, out, ldo, wmin, cbase, s);
+    else
+        pdf_scan_launch<kPInf, false>(pdf, N, n, qpf, Q, out, ldo, wmin, cbase, s);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ LB_Keogh of the survivors
 // One wave per item of G = 8 pairs of one query (the pass-0 survivors of list0).  The lanes walk
 // a candidate's row together, 64 consecutive elements per load, with the query envelope in

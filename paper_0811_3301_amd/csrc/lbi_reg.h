@@ -60,21 +60,33 @@ __device__ __forceinline__ float f4get(const float4 &v) {
 }
 
 // xs: this lane's staged row of x' (16-byte aligned); ys: the query values of the block's
-// outputs, ys[o] = y[e - W] for offset o (read only where an output exists).
-template <int P, int W, bool FIRST, bool PARTIAL>
-__device__ __forceinline__ void lbi_forward(float &acc, const float (&hx)[2 * W + 2], const float (&hn)[2 * W + 2],
-                                            const float4 *xs, const float4 *ys, int olim) {
+// outputs, ys[o] = y[e - W] for offset o (read only where an output exists).  Fused (F): xs holds
+// the raw row and us, ls the query envelope at the block's offsets; the clamp to the envelope is
+// taken here, and the LB_Keogh terms |x - x'|^p accumulate into s1 (positions past the series
+// are staged so that their term is zero).
+template <int P, int W, bool FIRST, bool PARTIAL, bool F>
+__device__ __forceinline__ void lbi_forward(float &acc, float &s1, const float (&hx)[2 * W + 2],
+                                            const float (&hn)[2 * W + 2], const float4 *xs, const float4 *ys,
+                                            const float4 *us, const float4 *ls, int olim) {
     constexpr int K = 2 * W + 1;
     constexpr int NG = (K + 3) / 4;
     float gx = -kInf, gn = kInf;
-    float4 xv[2], yv[2];
+    float4 xv[2], yv[2], uv[2], lv[2];
     xv[0] = xs[0];
     yv[0] = ys[0];
+    if constexpr (F) {
+        uv[0] = us[0];
+        lv[0] = ls[0];
+    }
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         if (g + 1 < NG) {
             xv[(g + 1) & 1] = xs[g + 1];
             yv[(g + 1) & 1] = ys[g + 1];
+            if constexpr (F) {
+                uv[(g + 1) & 1] = us[g + 1];
+                lv[(g + 1) & 1] = ls[g + 1];
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
         auto step = [&](auto tc) {
@@ -82,7 +94,12 @@ __device__ __forceinline__ void lbi_forward(float &acc, const float (&hx)[2 * W 
             const int o = 4 * g + t;
             if (o < K) {
                 if (PARTIAL && o >= olim) return false;  // uniform: the rest of the block is past the series
-                const float x = f4get<t>(xv[g & 1]);
+                float x = f4get<t>(xv[g & 1]);
+                if constexpr (F) {
+                    const float raw = x;
+                    x = __builtin_amdgcn_fmed3f(raw, f4get<t>(lv[g & 1]), f4get<t>(uv[g & 1]));
+                    s1 = pacc<P>(s1, raw - x);
+                }
                 gx = fmaxf(gx, x);
                 gn = fminf(gn, x);
                 if (!FIRST || o >= W) {  // in the first block, windows of o < W start before the series
@@ -103,23 +120,35 @@ __device__ __forceinline__ void lbi_forward(float &acc, const float (&hx)[2 * W 
 }
 
 // Suffix maximum and minimum of the staged block, in place (hx[K], hn[K] stay neutral), reading
-// the groups of four from the top, one group ahead.
-template <int W>
-__device__ __forceinline__ void lbi_suffix(float (&hx)[2 * W + 2], float (&hn)[2 * W + 2], const float4 *xs) {
+// the groups of four from the top, one group ahead (fused: clamping the raw row again).
+template <int W, bool F>
+__device__ __forceinline__ void lbi_suffix(float (&hx)[2 * W + 2], float (&hn)[2 * W + 2], const float4 *xs,
+                                           const float4 *us, const float4 *ls) {
     constexpr int K = 2 * W + 1;
     constexpr int NG = (K + 3) / 4;
-    float4 v[2];
+    float4 v[2], uv[2], lv[2];
     v[0] = xs[NG - 1];
+    if constexpr (F) {
+        uv[0] = us[NG - 1];
+        lv[0] = ls[NG - 1];
+    }
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
         const int g = NG - 1 - gi;
-        if (gi + 1 < NG) v[(gi + 1) & 1] = xs[g - 1];
+        if (gi + 1 < NG) {
+            v[(gi + 1) & 1] = xs[g - 1];
+            if constexpr (F) {
+                uv[(gi + 1) & 1] = us[g - 1];
+                lv[(gi + 1) & 1] = ls[g - 1];
+            }
+        }
         __builtin_amdgcn_sched_barrier(0);
         auto step = [&](auto tc) {
             constexpr int t = decltype(tc)::value;
             const int o = 4 * g + t;
             if (o < K) {
-                const float x = f4get<t>(v[gi & 1]);
+                float x = f4get<t>(v[gi & 1]);
+                if constexpr (F) x = __builtin_amdgcn_fmed3f(x, f4get<t>(lv[gi & 1]), f4get<t>(uv[gi & 1]));
                 hx[o] = fmaxf(hx[o + 1], x);
                 hn[o] = fminf(hn[o + 1], x);
             }
@@ -131,16 +160,23 @@ __device__ __forceinline__ void lbi_suffix(float (&hx)[2 * W + 2], float (&hn)[2
     }
 }
 
-template <int P, int W, int DEPTH>
+// F (fused): the list holds pass-0 survivors whose LB_Keogh has not been computed; the kernel
+// stages raw rows, clamps them itself and sums LB_Keogh along the way (Algorithm 3's first bound,
+// then its second, from one read of the row).  A pair counts in a.cntk[q] when its LB_Keogh
+// alone stays below the threshold, and a surviving pair's LB_Keogh goes to a.S1out[q][c] for
+// the DTW's abandon bound.  Early abandoning is off in this form (the counts need full sums).
+template <int P, int W, int DEPTH, bool F>
 __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
     constexpr int K = 2 * W + 1;
     extern __shared__ float sm[];
     const int n = a.n;
     constexpr int KB = lbi_blocks_per_stage<W>(), SK = lbi_seg<W>(), S = lbi_stride<W>();
     constexpr int SPAN = KB * K;      // positions staged together
-    float *stage = sm;                // [64][S]: x' of the stage's blocks, one row per pair
+    float *stage = sm;                // [64][S]: x' (raw x when F) of the stage's blocks, one row per pair
     float *ys = sm + 64 * S;          // [S]: y[e - W] of the stage's offsets
-    float *sY = ys + S;               // [n]
+    float *us = ys + S;               // F: [S] U, then [S] L at the stage's offsets
+    float *ls = us + (F ? S : 0);
+    float *sY = ls + (F ? S : 0);     // [n]
     const int lane = threadIdx.x;
     const int nblk = (n + W + K - 1) / K;
     const int nsb = (nblk + KB - 1) / KB;
@@ -160,8 +196,8 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
         const long long j = b * 64 + lane;
         const bool active = j < pair_count(a.pl, q, items.bk);
         const int c = active ? pair_cand(a.pl, q, j, items.bk) : 0;
-        const float s1 = active ? a.S1[q * a.ldS + c] : 0.f;
-        const bool abandon = a.abandon && a.thr && !a.out_root;
+        float s1 = (!F && active) ? a.S1[q * a.ldS + c] : 0.f;
+        const bool abandon = a.abandon && a.thr && !a.out_root && !F;
         const u64 tq = a.thr ? a.thr[q] : kNoKey;
         float hx[K + 1], hn[K + 1];
 #pragma unroll
@@ -199,12 +235,20 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
         };
         // position l of a stage (block l / K, offset l % K) goes to offset dst_of(l) of a row
         auto dst_of = [&](int l) { return l / K * SK + l % K; };
+        // F: a position past the series stages the clamped last value with an envelope of +-inf
+        // (its clamp is then the identity and its LB_Keogh term zero); others stage the raw value
         auto stage_from = [&](const auto &v, float u, float l, int e0) {
             if (lane < SPAN) {
                 const int dst = dst_of(lane);
+                const bool tail = e0 + lane >= n;
+                const float lo = (!F || tail) ? l : -kInf, hi = (!F || tail) ? u : kInf;
 #pragma unroll
-                for (int t = 0; t < (D >= 1 ? 64 : 1); ++t) stage[t * S + dst] = __builtin_amdgcn_fmed3f(v[t], l, u);
+                for (int t = 0; t < (D >= 1 ? 64 : 1); ++t) stage[t * S + dst] = __builtin_amdgcn_fmed3f(v[t], lo, hi);
                 ys[dst] = sY[min(max(e0 + lane - W, 0), n - 1)];
+                if constexpr (F) {
+                    us[dst] = tail ? kInf : u;
+                    ls[dst] = tail ? -kInf : l;
+                }
             }
         };
         auto stage_batched = [&](int e0) {
@@ -213,7 +257,15 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
                 const int er = min(e0 + r0 + lane, n - 1);
                 const float ur = Uq[er], lr = Lq[er];
                 const int dst = dst_of(r0 + lane);
-                if (r0 + lane < SPAN) ys[dst] = sY[min(max(e0 + r0 + lane - W, 0), n - 1)];
+                const bool tail = e0 + r0 + lane >= n;
+                const float lo = (!F || tail) ? lr : -kInf, hi = (!F || tail) ? ur : kInf;
+                if (r0 + lane < SPAN) {
+                    ys[dst] = sY[min(max(e0 + r0 + lane - W, 0), n - 1)];
+                    if constexpr (F) {
+                        us[dst] = tail ? kInf : ur;
+                        ls[dst] = tail ? -kInf : lr;
+                    }
+                }
 #pragma unroll 1
                 for (int j0 = 0; j0 < 64; j0 += 16) {
                     float v[16];
@@ -222,7 +274,7 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
                     if (r0 + lane < SPAN) {
 #pragma unroll
                         for (int t = 0; t < 16; ++t)
-                            stage[(j0 + t) * S + dst] = __builtin_amdgcn_fmed3f(v[t], lr, ur);
+                            stage[(j0 + t) * S + dst] = __builtin_amdgcn_fmed3f(v[t], lo, hi);
                     }
                 }
             }
@@ -233,18 +285,20 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
             const int olim = n + W - B * K;
             const float4 *xs = reinterpret_cast<const float4 *>(stage + lane * S + b * SK);
             const float4 *y4 = reinterpret_cast<const float4 *>(ys + b * SK);
+            const float4 *u4 = reinterpret_cast<const float4 *>(us + b * SK);
+            const float4 *l4 = reinterpret_cast<const float4 *>(ls + b * SK);
             if (B == 0) {
                 if (olim < K)
-                    lbi_forward<P, W, true, true>(acc, hx, hn, xs, y4, olim);
+                    lbi_forward<P, W, true, true, F>(acc, s1, hx, hn, xs, y4, u4, l4, olim);
                 else
-                    lbi_forward<P, W, true, false>(acc, hx, hn, xs, y4, olim);
+                    lbi_forward<P, W, true, false, F>(acc, s1, hx, hn, xs, y4, u4, l4, olim);
             } else if (olim < K) {
-                lbi_forward<P, W, false, true>(acc, hx, hn, xs, y4, olim);
+                lbi_forward<P, W, false, true, F>(acc, s1, hx, hn, xs, y4, u4, l4, olim);
             } else {
-                lbi_forward<P, W, false, false>(acc, hx, hn, xs, y4, olim);
+                lbi_forward<P, W, false, false, F>(acc, s1, hx, hn, xs, y4, u4, l4, olim);
             }
             if (abandon && B + 1 < nblk && __ballot(active && make_key(pjoin<P>(s1, acc), c) < tq) == 0) return true;
-            if (B + 1 < nblk) lbi_suffix<W>(hx, hn, xs);
+            if (B + 1 < nblk) lbi_suffix<W, F>(hx, hn, xs, u4, l4);
             return false;
         };
         // the blocks of stage sb in order; true when every pair of the wave has been abandoned
@@ -277,6 +331,11 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
         }
         const float s2 = pjoin<P>(s1, acc);
         if (a.out_root && active) a.out_root[c] = root_p<P>(s2);
+        if constexpr (F) {
+            const u64 mk = __ballot(active && make_key(s1, c) < tq);
+            if (lane == 0 && mk) atomicAdd(&a.cntk[q], __popcll(mk));
+            if (active && make_key(s2, c) < tq) a.S1out[q * a.ldS + c] = s1;
+        }
         if (a.thr) {
             const bool keep = active && make_key(s2, c) < a.thr[q];
             const u64 m = __ballot(keep);
@@ -293,16 +352,21 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
 template <int P, int W>
 static void lbi_reg_launch(int num_cu, const LbiArgs &a, hipStream_t s) {
     constexpr int K = 2 * W + 1;
-    const size_t lds = sizeof(float) * ((size_t)a.n + 65 * (size_t)lbi_stride<W>());
-#define LBIMP_LBI_REG(DD) \
-    hipLaunchKernelGGL((k_lbi_reg<P, W, DD>), dim3(persistent_grid(k_lbi_reg<P, W, DD>, lds, num_cu)), dim3(64), lds, s, a)
+    const size_t lds = sizeof(float) * ((size_t)a.n + (a.fused ? 67 : 65) * (size_t)lbi_stride<W>());
+#define LBIMP_LBI_REG(DD, FF)                                                                                     \
+    hipLaunchKernelGGL((k_lbi_reg<P, W, DD, FF>), dim3(persistent_grid(k_lbi_reg<P, W, DD, FF>, lds, num_cu)), \
+                       dim3(64), lds, s, a)
+    if (a.fused) {  // one depth: blocks loaded ahead where they fit
+        LBIMP_LBI_REG(K <= 64 ? 1 : 0, true);
+        return;
+    }
     if constexpr (K <= 64) {
         if (a.pipeline) {
-            LBIMP_LBI_REG(1);
+            LBIMP_LBI_REG(1, false);
             return;
         }
     }
-    LBIMP_LBI_REG(0);
+    LBIMP_LBI_REG(0, false);
 #undef LBIMP_LBI_REG
 }
 

@@ -139,7 +139,7 @@ static void chunked_and_noalloc() {
         OK(lbimp_ctx_set_option(ctx, "workspace_limit", limit));
         for (int k : {1, 3})
             for (int mode = LBIMP_MODE_BRUTE; mode <= LBIMP_MODE_IMPROVED; ++mode)
-                for (int pd : {0, 1})
+                for (int pd : {0, 1, 2})
                     for (int p : {1, 2, LBIMP_P_INF}) {
                         OK(lbimp_ctx_set_option(ctx, "pd_prefilter", pd));
                         OK(lbimp_ctx_set_option(ctx, "lbi_buckets", ((p & 3) + pd + k) & 1));
@@ -154,6 +154,9 @@ static void chunked_and_noalloc() {
         if (limit == (8 << 20))
             CHECK(ws_bytes(ctx) <= (uint64_t)limit + limit / 8 + (1 << 20), "workspace %llu above the bound",
                   (unsigned long long)ws_bytes(ctx));
+        OK(lbimp_ctx_set_option(ctx, "pd_fine", 1));
+        OK(lbimp_db_pd_bound(ctx, db, qs, qs, Q, 2, dev<float>(Q * N)));
+        OK(lbimp_ctx_set_option(ctx, "pd_fine", 0));
         int32_t choice[LBIMP_TUNE_KNOBS];
         OK(lbimp_autotune(ctx, db, qs, Q, 13, 1, 3, LBIMP_MODE_IMPROVED, choice));
         OK(lbimp_ctx_set_option(ctx, "autotune", 1));
@@ -198,6 +201,11 @@ static void invalid_arguments() {
     CHECK(lbimp_ctx_set_option(ctx, "no such option", 1) == LBIMP_E_INVALID, "unknown option accepted");
     CHECK(lbimp_ctx_set_option(ctx, "workspace_limit", -1) == LBIMP_E_INVALID, "negative bound accepted");
     CHECK(lbimp_ctx_set_option(ctx, "seeds", 65) == LBIMP_E_INVALID, "65 seeds accepted");
+    CHECK(lbimp_ctx_set_option(ctx, "pd_prefilter", 3) == LBIMP_E_INVALID, "pass-0 form 3 accepted");
+    OK(lbimp_ctx_set_option(ctx, "pd_fine", 1));
+    CHECK(lbimp_db_pd_bound(ctx, db, x, x, 1, 1, dev<float>(100)) == LBIMP_E_UNSUPPORTED,
+          "fine cover accepted for n = 10");
+    OK(lbimp_ctx_set_option(ctx, "pd_fine", 0));
     CHECK(lbimp_ctx_set_option(ctx, "lbi_pipeline", 2) == LBIMP_E_INVALID, "pipeline depth 2 accepted");
     // k above N: every slot past the N neighbours is empty, not an error
     OK(lbimp_nn_search(ctx, db, x, 1, 3, 1, 64, 2, idx, dist, nullptr));

@@ -225,26 +225,75 @@ def test_db_pd_bound(L, ctx, N, n, p):
     db.close()
 
 
+@pytest.mark.parametrize("N,n", [(300, 64), (65, 131), (1000, 256), (70, 1000), (129, 100)])
+@pytest.mark.parametrize("p", [1, 2, INF])
+def test_db_pd_bound_fine(L, ctx, N, n, p):
+    """The 32-part cover in fp32: never above the oracle's exact bound on the same cover (the
+    rounding margins), within a few parts per million of it, and below LB_Keogh."""
+    _say(f"db_pd_bound fine N={N} n={n} p={p}")
+    X = walks(N, n, 52)
+    Ys = walks(3, n, 53)
+    w = max(0, n // 10)
+    db = L.Db(ctx, to_dev(X))
+    env = [R.envelope_naive(Ys[q], w) for q in range(3)]
+    L.lbimp_ctx_set_option(ctx, "pd_fine", 1)
+    try:
+        lb = L.lbimp_db_pd_bound(ctx, db, to_dev(np.stack([e[0] for e in env])),
+                                 to_dev(np.stack([e[1] for e in env])), p).cpu().numpy().astype(np.float64)
+    finally:
+        L.lbimp_ctx_set_option(ctx, "pd_fine", 0)
+    for q in range(3):
+        want = rt(R.pd_bound_pow_many(X, env[q][0], env[q][1], p, d=32), p)
+        scale = lp_scale(X, Ys[q], p)
+        assert np.all(lb[q] <= want), f"fine bound above the exact one, q={q}"
+        assert np.all(want - lb[q] <= 2e-5 * scale + 1e-6), f"fine bound too loose, q={q}"
+        s1, _ = native.lb_many(X, Ys[q], w, p)
+        assert np.all(lb[q] <= rt(s1, p) * (1 + 1e-6) + 1e-6)  # below LB_Keogh
+    db.close()
+
+
+def test_db_pd_bound_fine_short_series(L, ctx):
+    """No 32-part sums below 64 samples: the fine bound is refused, the 8-part one works."""
+    X = walks(50, 40, 54)
+    db = L.Db(ctx, to_dev(X))
+    U = to_dev(X[:1])
+    L.lbimp_ctx_set_option(ctx, "pd_fine", 1)
+    try:
+        with pytest.raises(L.LbimpError):
+            L.lbimp_db_pd_bound(ctx, db, U, U, 1)
+    finally:
+        L.lbimp_ctx_set_option(ctx, "pd_fine", 0)
+    L.lbimp_db_pd_bound(ctx, db, U, U, 1)
+    db.close()
+
+
+def fine_parts(pd, mode, n, w):
+    """Parts of the pass-0 cover a search uses: 32 where the fine flow applies, else 8."""
+    return 32 if (pd == 2 and mode == "improved" and n >= 64 and R.effective_band(n, w) <= 52) else 8
+
+
 @pytest.mark.parametrize("mode", ["keogh", "improved"])
 @pytest.mark.parametrize("p,k", [(1, 1), (2, 3), (INF, 2), (1, 10)])
-@pytest.mark.parametrize("n,w", [(128, 13), (200, 80), (37, 4)])
-def test_nn_search_pd_prefilter(L, ctx, mode, p, k, n, w):
-    """Pass 0 (piecewise sums) ahead of LB_Keogh: the same answers, bit for bit, as without it,
-    matching the oracle; the pass prunes on random walks; counts stay within the invariants."""
-    _say(f"nn_search pd_prefilter mode={mode} p={p} k={k} n={n} w={w}")
+@pytest.mark.parametrize("n,w", [(128, 13), (200, 80), (37, 4), (256, 26), (64, 6), (100, 52)])
+@pytest.mark.parametrize("pd", [1, 2])
+def test_nn_search_pd_prefilter(L, ctx, mode, p, k, n, w, pd):
+    """Pass 0 (piecewise sums, 8 parts ahead of LB_Keogh, or 32 parts with LB_Keogh computed
+    inside LB_Improved): the same answers, bit for bit, as without it, matching the oracle; the
+    pass prunes on random walks; counts stay within the invariants of the cover used."""
+    _say(f"nn_search pd_prefilter={pd} mode={mode} p={p} k={k} n={n} w={w}")
     X = walks(3000, n, 34)
     Ys = walks(7, n, 35)
     db = L.Db(ctx, to_dev(X))
     Yd = to_dev(Ys)
     ri, rd, _ = L.lbimp_nn_search(ctx, db, Yd, w, p, k, mode)
-    L.lbimp_ctx_set_option(ctx, "pd_prefilter", 1)
+    L.lbimp_ctx_set_option(ctx, "pd_prefilter", pd)
     try:
         idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, p, k, mode)
     finally:
         L.lbimp_ctx_set_option(ctx, "pd_prefilter", 0)
     assert torch.equal(idx, ri) and torch.equal(dist, rd)
     check_knn(X, Ys, w, p, k, idx.cpu().numpy(), dist.cpu().numpy(), f"pd {mode} p={p} k={k}")
-    check_stats(X, Ys, w, p, st, mode, pd=True)
+    check_stats(X, Ys, w, p, st, mode, pd=True, pd_parts=fine_parts(pd, mode, n, w))
     assert st[:, 6].sum() > 0
     db.close()
 
@@ -322,7 +371,7 @@ def test_nn_search_lbi_pipeline_depth(L, ctx, depth, n, w):
 
 @pytest.mark.parametrize("mode", ["brute", "keogh", "improved"])
 @pytest.mark.parametrize("p,k", [(1, 1), (2, 5), (INF, 3)])
-@pytest.mark.parametrize("pd", [0, 1])
+@pytest.mark.parametrize("pd", [0, 1, 2])
 def test_nn_search_chunked(L, ctx, mode, p, k, pd):
     """A workspace bound splits the database into chunks of candidates searched one after another
     (the threshold carried across): the answers equal the unchunked search's, bit for bit, and the
@@ -348,7 +397,7 @@ def test_nn_search_chunked(L, ctx, mode, p, k, pd):
         L.lbimp_ctx_set_option(ctx, "pd_prefilter", 0)
     assert torch.equal(idx, ri) and torch.equal(dist, rd)
     check_knn(X, Ys, 6, p, k, idx.cpu().numpy(), dist.cpu().numpy(), f"chunked {mode} p={p} k={k}")
-    check_stats(X, Ys, 6, p, st, mode, pd=bool(pd))
+    check_stats(X, Ys, 6, p, st, mode, pd=bool(pd), pd_parts=fine_parts(pd, mode, 64, 6))
     if mode != "brute":
         assert np.all(st[:, 1] > 32)  # seeds drawn in every chunk: several chunks ran
     db.close()
@@ -416,7 +465,7 @@ def check_golden(name, X, Ys, w, p, gidx, gdist):
     return rel
 
 
-def check_stats(X, Ys, w, p, st, mode, pd=False):
+def check_stats(X, Ys, w, p, st, mode, pd=False, pd_parts=8):
     """Counts relative to the exact final threshold b*: the device threshold is never below b*,
     so it prunes no candidate whose bound is below b* (up to float32 rounding).  The bounds are
     nested (P_d <= LB_Keogh <= LB_Improved), so each pass's cumulative count is checked against
@@ -439,7 +488,7 @@ def check_stats(X, Ys, w, p, st, mode, pd=False):
         slack = 1 + 1e-4
         if pd:
             U, Lo = R.envelope_naive(Ys[q], wb)
-            b0 = R.pd_bound_pow_many(X, U, Lo, p)
+            b0 = R.pd_bound_pow_many(X, U, Lo, p, d=pd_parts)
             assert ppd <= np.sum(b0 * slack >= bstar)
         assert ppd + pk <= np.sum(s1 * slack >= bstar)
         assert ppd + pk + pi <= np.sum(s2 * slack >= bstar)
