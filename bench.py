@@ -30,21 +30,25 @@ METRIC = "1-NN DTW queries/sec (LB_Improved vs LB_Keogh vs brute); LB GB/s; p50/
 # accumulate: 3 instructions; an LB_Improved element about 9 (clamp, the running and block
 # max/min of the projection's envelope, the distance of y to it, the accumulate).  A model of
 # the issue cost, kept beside the count: a 3-operand med3/min3 issues in two slots, so an
-# LB_Keogh element or a DTW cell costs 4 slots.
+# LB_Keogh element or a DTW cell costs 4 slots.  Pass 0 on the 32-part cover costs per (query,
+# candidate) 3 instructions per part (clamp, subtract, accumulate), and reads 128 bytes of sums
+# per candidate; with it, LB_Improved computes LB_Keogh too: 3 + 9 per element.
 VALU_PEAK = 157.3e12 / 2
 HBM_PEAK_GBPS = 8000.0
 LBK_INSTR_PER_ELEM = 3
 LBK_SLOTS_PER_ELEM_MODEL = 4
 DTW_INSTR_PER_CELL = 3
 LBI_INSTR_PER_ELEM = 9
+PD_FINE_PARTS = 32
+PDF_INSTR_PER_PART = 3
 
 
-def sweep_traffic():
-    """HBM bytes per sweep launch from the committed PMC summary, if it was taken on the
-    current sweep kernel source (else None)."""
+def sweep_traffic(profile="lbk_sweep_rw256_traffic.md", source="kernels_lb.hip"):
+    """HBM bytes per launch of a kernel from its committed PMC summary under profiles/, if it was
+    taken on the current source of that kernel (else None)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_0811_3301_amd", "csrc", "kernels_lb.hip")
-    prof = os.path.join(ROOT, "profiles", "lbk_sweep_rw256_traffic.md")
+    src = os.path.join(ROOT, "paper_0811_3301_amd", "csrc", source)
+    prof = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(prof):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -101,23 +105,39 @@ def time_mode(L, ctx, db, Yd, w, p, mode, steps, warmup):
                 idx=idx_h.numpy()[:, 0].copy(), dist=dist_h.numpy()[:, 0].copy())
 
 
-def t_roof(mode, Q, N, n, w, st):
-    """Roofline time of one step from the measured counts: max(HBM bytes of the database read
-    once, 3 instructions per LB_Keogh element of every pair) + (9 per LB_Improved element of
-    every pass-1 survivor + 3 per DTW cell) / VALU peak.  DTW cells: every cell of the DTWs
-    that ran to the end, plus those that were abandoned counted at 0 cells (low) or in full
-    (high); the two bracket the cells actually computed."""
+def stage_work(mode, Q, N, n, w, st, pd=0):
+    """Algorithmic work of the stages of one step from the measured counts: (instructions, HBM
+    bytes) of the first pass, instructions of LB_Improved, and the DTW instructions bracketed
+    low/high.  First pass: 3 instructions per LB_Keogh element of every pair and the database
+    read once, or with pass 0 on the 32-part cover (pd = 2) 3 per part of every pair and its
+    128-byte sums per candidate.  LB_Improved: 9 per element of every pass-1 survivor, or with
+    pd = 2 (3 + 9) per element of every pass-0 survivor (LB_Keogh computed there).  DTW: 3 per
+    cell of the DTWs that ran to the end, plus those that were abandoned counted at 0 cells (low)
+    or in full (high); the two bracket the cells actually computed."""
     cells = n * (2 * w + 1) - w * (w + 1)
     started, abandoned = float(st[:, 4].sum()), float(st[:, 5].sum())
+    dtw = (DTW_INSTR_PER_CELL * cells * (started - abandoned), DTW_INSTR_PER_CELL * cells * started)
     if mode == "brute":
-        base = 0.0
-        lbi = 0.0
+        return dict(first=(0.0, 0.0), lbi=0.0, dtw=dtw)
+    if pd == 2 and mode == "improved":
+        first = (PDF_INSTR_PER_PART * PD_FINE_PARTS * Q * N, N * PD_FINE_PARTS * 4)
+        survivors0 = float((st[:, 0] - st[:, 1] - st[:, 6]).sum())  # pass-0 survivors (seeds excluded)
+        lbi = (LBK_INSTR_PER_ELEM + LBI_INSTR_PER_ELEM) * n * survivors0
     else:
-        base = max(N * n * 4 / (HBM_PEAK_GBPS * 1e9), LBK_INSTR_PER_ELEM * Q * N * n / VALU_PEAK)
+        first = (LBK_INSTR_PER_ELEM * Q * N * n, N * n * 4)
         survivors1 = float((st[:, 3] + st[:, 4] - st[:, 1]).sum())  # pass-1 survivors (seeds excluded)
-        lbi = LBI_INSTR_PER_ELEM * n * survivors1 / VALU_PEAK if mode == "improved" else 0.0
-    lo = base + lbi + DTW_INSTR_PER_CELL * cells * (started - abandoned) / VALU_PEAK
-    hi = base + lbi + DTW_INSTR_PER_CELL * cells * started / VALU_PEAK
+        lbi = LBI_INSTR_PER_ELEM * n * survivors1 if mode == "improved" else 0.0
+    return dict(first=first, lbi=lbi, dtw=dtw)
+
+
+def t_roof(mode, Q, N, n, w, st, pd=0):
+    """Roofline time of one step from the measured counts (stage_work): max(first-pass HBM
+    bytes / HBM peak, first-pass instructions / VALU peak) + (LB_Improved + DTW instructions) /
+    VALU peak, with the DTW bracketed low/high."""
+    wk = stage_work(mode, Q, N, n, w, st, pd)
+    base = max(wk["first"][1] / (HBM_PEAK_GBPS * 1e9), wk["first"][0] / VALU_PEAK)
+    lo = base + (wk["lbi"] + wk["dtw"][0]) / VALU_PEAK
+    hi = base + (wk["lbi"] + wk["dtw"][1]) / VALU_PEAK
     return lo * 1e3, hi * 1e3
 
 
@@ -609,6 +629,14 @@ def main():
         name, value = kv.split("=", 1)
         L.lbimp_ctx_set_option(ctx, name, int(value))
 
+    # the headline's tuned choices, recorded (the searches below find them and tune nothing)
+    set_opts = {k: int(v) for k, v in (kv.split("=", 1) for kv in args.set)}
+    knobs = {}
+    for mode in ("improved", "keogh"):
+        knobs[mode] = None if args.no_autotune else L.lbimp_autotune(ctx, db, Yd, w, 1, 1, mode)
+    pd_of = {m: (kn["pd"] if kn else set_opts.get("pd_prefilter", 0)) for m, kn in knobs.items()}
+    pd_of["brute"] = 0
+
     log("timing two-pass p=1")
     imp = time_mode(L, ctx, db, Yd, w, 1, "improved", args.steps, args.warmup)
     gpu_idx = imp["idx"]
@@ -616,7 +644,7 @@ def main():
     stages = stage_profile(L, ctx, db, Yd, w, 1, "improved", max(3, args.steps // 2))
 
     def mode_entry(r, stats, mode):
-        lo, hi = t_roof(mode, Q, N, n, w, stats)
+        lo, hi = t_roof(mode, Q, N, n, w, stats, pd_of[mode])
         return dict(qps=Q / (r["ms_per_step"] / 1e3), ms_per_step=r["ms_per_step"],
                     t_roof_ms=[lo, hi], roof_frac=[lo / r["ms_per_step"], hi / r["ms_per_step"]])
 
@@ -641,16 +669,42 @@ def main():
     else:
         p2 = None
 
-    sweep_ms = stages["lb_keogh"]
+    # rooflines of the stages of the tuned two-pass step; the bench line reports the longest
+    wk = stage_work("improved", Q, N, n, w, st, pd_of["improved"])
+    fine = pd_of["improved"] == 2
+
+    def roof(kernel, ms, instr, **extra):
+        achieved = instr / (ms / 1e3)
+        return dict(kernel=kernel, bound="alu", kernel_ms=ms, instructions=instr, achieved=achieved / 1e12,
+                    peak=VALU_PEAK / 1e12, unit="T VALU lane-instructions/s", frac=achieved / VALU_PEAK, **extra)
+
     elems = Q * N * n
-    achieved = LBK_INSTR_PER_ELEM * elems / (sweep_ms / 1e3) / 1e12
-    roofline = dict(bound="alu", kernel="k_lbk_sweep (LB_Keogh of every query x candidate)",
-                    achieved=achieved, peak=VALU_PEAK / 1e12, unit="T VALU lane-instructions/s",
-                    frac=achieved * 1e12 / VALU_PEAK, traffic=sweep_traffic(), kernel_ms=sweep_ms,
-                    instructions_per_element=LBK_INSTR_PER_ELEM, elements=elems,
-                    frac_issue_model=LBK_SLOTS_PER_ELEM_MODEL * elems / (sweep_ms / 1e3) / VALU_PEAK,
-                    issue_model="med3 issues in two slots: 4 slots per element",
-                    algorithmic_hbm_bytes=N * n * 4 + Q * ((N + 63) // 64 * 64) * 4)
+    if fine:
+        first = roof("k_pdf_scan (pass 0: 32-part piecewise-sum bound of every query x candidate)",
+                     stages["lb_keogh"], wk["first"][0], instructions_per_pair=PDF_INSTR_PER_PART * PD_FINE_PARTS,
+                     pairs=Q * N, algorithmic_hbm_bytes=wk["first"][1] + Q * ((N + 63) // 64 * 64) * 4)
+    else:
+        first = roof("k_lbk_sweep (LB_Keogh of every query x candidate)", stages["lb_keogh"], wk["first"][0],
+                     instructions_per_element=LBK_INSTR_PER_ELEM, elements=elems,
+                     frac_issue_model=LBK_SLOTS_PER_ELEM_MODEL * elems / (stages["lb_keogh"] / 1e3) / VALU_PEAK,
+                     issue_model="med3 issues in two slots: 4 slots per element",
+                     algorithmic_hbm_bytes=N * n * 4 + Q * ((N + 63) // 64 * 64) * 4)
+    lbi_pairs = float((st[:, 0] - st[:, 1] - st[:, 6]).sum()) if fine else float((st[:, 3] + st[:, 4] - st[:, 1]).sum())
+    second = roof("k_lbi_reg (LB_Improved" + (" with LB_Keogh, of every pass-0 survivor)" if fine else
+                                              " of every pass-1 survivor)"),
+                  stages["lb_improved"], wk["lbi"],
+                  instructions_per_element=(LBK_INSTR_PER_ELEM if fine else 0) + LBI_INSTR_PER_ELEM,
+                  pairs=lbi_pairs, row_bytes=lbi_pairs * n * 4)
+    dtw = roof("k_dtw_lane (DTW of the survivors, abandoned DTWs counted in full)", stages["dtw"], wk["dtw"][1],
+               frac_low=wk["dtw"][0] / (stages["dtw"] / 1e3) / VALU_PEAK)
+    stage_roofs = {"first_pass": first, "lb_improved": second, "dtw": dtw}
+    dom = max(stage_roofs, key=lambda k_: stage_roofs[k_]["kernel_ms"])
+    traffic = None
+    if dom == "first_pass" and not fine:
+        traffic = sweep_traffic()
+    elif dom == "lb_improved" and fine:
+        traffic = sweep_traffic("lbi_fused_rw256_traffic.md", "lbi_reg.h")
+    roofline = dict(stage_roofs[dom], traffic=traffic, stage=dom)
     if "brute" in modes:
         cells = Q * N * (n * (2 * w + 1) - w * (w + 1))
         t = modes["brute"]["ms_per_step"] / 1e3
@@ -726,7 +780,8 @@ def main():
                            dtw_fraction=float(st[:, 4].sum() / (N * Q)),
                            abandoned_fraction_of_dtw=float(st[:, 5].sum() / max(1, st[:, 4].sum()))),
         "stage_ms_p1": stages,
-        "headline_options": {"autotune": not args.no_autotune, "set": args.set},
+        "headline_options": {"autotune": not args.no_autotune, "set": args.set, "tuned": knobs},
+        "stage_rooflines_p1": stage_roofs,
         "accuracy_vs_oracle": accuracy,
         "lb_single_query_hbm": lbg,
         "pd_prefilter": pdb,

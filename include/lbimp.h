@@ -257,8 +257,9 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
  * "autotune" set, those calls tune a shape they meet for the first time by themselves.
  * choice: host [LBIMP_TUNE_KNOBS] or NULL, receives {seeds, sweep_shape, lbi_pipeline,
  * survivors' DTW group-per-pair, seeding DTW lane-per-pair, abandon bound with the LB_Keogh
- * tail, pass 0 with the piecewise-sum bound, early abandoning in LB_Improved, LB_Improved over
- * survivor lists bucketed by candidate range}.  Waits for the stream. */
+ * tail, pass 0 with the piecewise-sum bound (the value of option "pd_prefilter": 0, 1 or 2),
+ * early abandoning in LB_Improved, LB_Improved over survivor lists bucketed by candidate
+ * range}.  Waits for the stream. */
 #define LBIMP_TUNE_KNOBS 9
 int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                    int32_t k, int32_t mode, int32_t *choice);

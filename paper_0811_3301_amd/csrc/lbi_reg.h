@@ -62,33 +62,31 @@ __device__ __forceinline__ float f4get(const float4 &v) {
 // xs: this lane's staged row of x' (16-byte aligned); ys: the query values of the block's
 // outputs, ys[o] = y[e - W] for offset o (read only where an output exists).  Fused (F): xs holds
 // the raw row and us, ls the query envelope at the block's offsets; the clamp to the envelope is
-// taken here, and the LB_Keogh terms |x - x'|^p accumulate into s1 (positions past the series
-// are staged so that their term is zero).
+// taken here, the LB_Keogh terms |x - x'|^p accumulate into s1 (positions past the series are
+// staged so that their term is zero), and x' is written back over the raw row group by group for
+// the suffix pass (which a last, partial block does not need).
 template <int P, int W, bool FIRST, bool PARTIAL, bool F>
 __device__ __forceinline__ void lbi_forward(float &acc, float &s1, const float (&hx)[2 * W + 2],
-                                            const float (&hn)[2 * W + 2], const float4 *xs, const float4 *ys,
+                                            const float (&hn)[2 * W + 2], float4 *xs, const float4 *ys,
                                             const float4 *us, const float4 *ls, int olim) {
     constexpr int K = 2 * W + 1;
     constexpr int NG = (K + 3) / 4;
     float gx = -kInf, gn = kInf;
-    float4 xv[2], yv[2], uv[2], lv[2];
+    float4 xv[2], yv[2], uv, lv;  // F: the envelope of the current group only (registers are short)
     xv[0] = xs[0];
     yv[0] = ys[0];
-    if constexpr (F) {
-        uv[0] = us[0];
-        lv[0] = ls[0];
-    }
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
+        if constexpr (F) {
+            uv = us[g];
+            lv = ls[g];
+        }
         if (g + 1 < NG) {
             xv[(g + 1) & 1] = xs[g + 1];
             yv[(g + 1) & 1] = ys[g + 1];
-            if constexpr (F) {
-                uv[(g + 1) & 1] = us[g + 1];
-                lv[(g + 1) & 1] = ls[g + 1];
-            }
         }
         __builtin_amdgcn_sched_barrier(0);
+        float4 xo = xv[g & 1];  // F: this group's x'
         auto step = [&](auto tc) {
             constexpr int t = decltype(tc)::value;
             const int o = 4 * g + t;
@@ -97,8 +95,12 @@ __device__ __forceinline__ void lbi_forward(float &acc, float &s1, const float (
                 float x = f4get<t>(xv[g & 1]);
                 if constexpr (F) {
                     const float raw = x;
-                    x = __builtin_amdgcn_fmed3f(raw, f4get<t>(lv[g & 1]), f4get<t>(uv[g & 1]));
+                    x = __builtin_amdgcn_fmed3f(raw, f4get<t>(lv), f4get<t>(uv));
                     s1 = pacc<P>(s1, raw - x);
+                    if constexpr (t == 0) xo.x = x;
+                    if constexpr (t == 1) xo.y = x;
+                    if constexpr (t == 2) xo.z = x;
+                    if constexpr (t == 3) xo.w = x;
                 }
                 gx = fmaxf(gx, x);
                 gn = fminf(gn, x);
@@ -116,6 +118,7 @@ __device__ __forceinline__ void lbi_forward(float &acc, float &s1, const float (
         if (!step(std::integral_constant<int, 1>{})) return;
         if (!step(std::integral_constant<int, 2>{})) return;
         if (!step(std::integral_constant<int, 3>{})) return;
+        if constexpr (F) xs[g] = xo;
     }
 }
 
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
         // max/min of the block in place; true when every pair of the wave has been abandoned
         auto compute_block = [&](int B, int b) __attribute__((always_inline)) -> bool {
             const int olim = n + W - B * K;
-            const float4 *xs = reinterpret_cast<const float4 *>(stage + lane * S + b * SK);
+            float4 *xs = reinterpret_cast<float4 *>(stage + lane * S + b * SK);
             const float4 *y4 = reinterpret_cast<const float4 *>(ys + b * SK);
             const float4 *u4 = reinterpret_cast<const float4 *>(us + b * SK);
             const float4 *l4 = reinterpret_cast<const float4 *>(ls + b * SK);
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
                 lbi_forward<P, W, false, false, F>(acc, s1, hx, hn, xs, y4, u4, l4, olim);
             }
             if (abandon && B + 1 < nblk && __ballot(active && make_key(pjoin<P>(s1, acc), c) < tq) == 0) return true;
-            if (B + 1 < nblk) lbi_suffix<W, F>(hx, hn, xs, u4, l4);
+            if (B + 1 < nblk) lbi_suffix<W, false>(hx, hn, xs, u4, l4);  // x' is in the stage now
             return false;
         };
         // the blocks of stage sb in order; true when every pair of the wave has been abandoned

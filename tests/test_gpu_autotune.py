@@ -28,8 +28,9 @@ def test_autotune_choice_keeps_results(L, n, w, mode, k):
         ref_i, ref_d, ref_s = L.lbimp_nn_search(ctx, db, Yd, w, 1, k, mode)
         choice = L.lbimp_autotune(ctx, db, Yd, w, 1, k, mode)
         assert choice["seeds"] in (8, 16, 32, 64) and 0 <= choice["sweep_shape"] <= 5
-        assert all(choice[key] in (0, 1) for key in ("lbi_pipeline", "dtw_group", "seed_lane", "cascade", "pd",
+        assert all(choice[key] in (0, 1) for key in ("lbi_pipeline", "dtw_group", "seed_lane", "cascade",
                                                              "lbi_abandon", "lbi_buckets"))
+        assert choice["pd"] in (0, 1, 2)
         got_i, got_d, got_s = L.lbimp_nn_search(ctx, db, Yd, w, 1, k, mode)  # runs with the tuned choice
         assert torch.equal(ref_i, got_i)
         assert np.array_equal(ref_d.cpu().numpy().view(np.uint32), got_d.cpu().numpy().view(np.uint32))

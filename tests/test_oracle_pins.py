@@ -169,10 +169,34 @@ def test_pd_bound():
 
 def test_pd_bound_many_matches_rows():
     g = np.random.default_rng(22)
-    for n, w, d in ((50, 5, 8), (7, 3, 8), (131, 13, 8), (64, 0, 4)):
+    for n, w, d in ((50, 5, 8), (7, 3, 8), (131, 13, 8), (64, 0, 4), (256, 26, 32), (100, 10, 32)):
         X = np.cumsum(g.standard_normal((30, n)), axis=1)
         U, L = R.envelope_naive(np.cumsum(g.standard_normal(n)), w)
         for p in (1, 2, math.inf):
             many = R.pd_bound_pow_many(X, U, L, p, d)
             for c in range(X.shape[0]):
                 assert P._rel_close(many[c], R.pd_bound_pow(X[c], U, L, p, d), 1e-12)
+
+
+def test_pd_fine_cover():
+    """The 32-part cover of the fp32 first pass: P_32 <= LB_Keogh <= DTW for every p; for p = 1
+    on nested covers (n a multiple of 32) refining the 8 parts into 32 never lowers the bound,
+    since the distance of a sum over a union of parts is at most the sum of the parts' distances;
+    and n = 32 (one element per part) gives LB_Keogh exactly."""
+    g = np.random.default_rng(23)
+    for t in range(40):
+        n = int(g.choice([64, 96, 128, 256, 100, 131]))
+        w = int(g.integers(0, n // 4 + 1))
+        x = np.cumsum(g.standard_normal(n))
+        y = np.cumsum(g.standard_normal(n))
+        U, L = R.envelope_naive(y, w)
+        for p in (1, 2, math.inf):
+            b32 = R.pd_bound_pow(x, U, L, p, 32)
+            k = R.lb_keogh_pow(x, U, L, p)
+            assert -1e-12 <= b32 <= k * (1 + 1e-12) + 1e-12, (n, w, p)
+        if n % 32 == 0:
+            assert R.pd_bound_pow(x, U, L, 1, 32) >= R.pd_bound_pow(x, U, L, 1, 8) * (1 - 1e-12) - 1e-12
+    x = np.cumsum(g.standard_normal(32))
+    U, L = R.envelope_naive(np.cumsum(g.standard_normal(32)), 3)
+    for p in (1, 2, math.inf):
+        assert P._rel_close(R.pd_bound_pow(x, U, L, p, 32), R.lb_keogh_pow(x, U, L, p), 1e-12)
