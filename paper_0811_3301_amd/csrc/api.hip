@@ -260,7 +260,7 @@ static void chunk_dims(const SearchSpec &sp, int64_t C, SearchDims &d) {
     d.S = d.brute ? 0 : (int)std::min<int64_t>(std::max(sp.kn.seeds, sp.k), d.C);
     // result keys: the k kept from earlier chunks, then the seeds' and the survivors' of a chunk
     d.ldres = d.brute ? std::max<int64_t>(d.C, 1) + (d.nchunks > 1 ? d.k : 0) : d.S + d.C + (d.nchunks > 1 ? d.k : 0);
-    d.nw = d.pd ? pd_scan_waves(d.C) : sweep_waves(sp.kn.sweep_shape, d.C, sp.Q);
+    d.nw = d.fine ? pdf_scan_waves(d.C) : d.pd ? pd_scan_waves(d.C) : sweep_waves(sp.kn.sweep_shape, d.C, sp.Q);
     // seeds come from the per-wave minima of the sweep once there are enough of them
     d.from_minima = !d.brute && d.nw >= 4 * (int64_t)kMaxSeeds;
     // LB_Improved survivors bucketed by candidate range: about 2 MiB of rows per bucket, so that
@@ -443,7 +443,8 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
             }
             stage_first(2);
             const int Sj = (int)std::min<int64_t>(d.S, cj);
-            const int64_t nwj = d.pd ? pd_scan_waves(cj) : sweep_waves(sp.kn.sweep_shape, cj, Q);
+            const int64_t nwj =
+                d.fine ? pdf_scan_waves(cj) : d.pd ? pd_scan_waves(cj) : sweep_waves(sp.kn.sweep_shape, cj, Q);
             const bool minima = d.from_minima && nwj >= 4 * (int64_t)kMaxSeeds;
             HIPTRY(launch_select_seeds(S1v, d.Np, c1, Q, Sj, minima ? b.wmin : nullptr, nwj, b.seeds, s, c0));
             stage_first(3);

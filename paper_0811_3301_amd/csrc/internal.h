@@ -93,8 +93,9 @@ hipError_t launch_pd_scan(int p, const double *pd, int64_t N, int n, const doubl
 // The same bound on the fine cover (kPdFine parts, fp32, with rounding margins that keep it below
 // the exact bound): pdf [ceil(N/64)][kPdFine/4][64] float4 interleaved sums of a database's
 // rows; qpf [Q][kPdfQuery] the query envelopes' sums and margins.  The scan writes out[q][c] and
-// the per-wave minima wmin[q][v] (v < pd_scan_waves(N)) like launch_pd_scan; the fine table is
+// the per-wave minima wmin[q][v] of 128 candidates each (v < pdf_scan_waves(N)); the fine table is
 // addressed by 64-candidate tiles, so a chunk's cbase must be a multiple of 64.
+int64_t pdf_scan_waves(int64_t N);
 hipError_t launch_pdf_rows(const float *rows, int64_t N, int n, float4 *pdf, hipStream_t s);
 hipError_t launch_pdf_query(const float *U, const float *L, int ldq, int64_t Q, int n, float *qpf, hipStream_t s);
 hipError_t launch_pdf_scan(int p, const float4 *pdf, int64_t N, int n, const float *qpf, int64_t Q, float *out,

@@ -248,9 +248,10 @@ hipError_t launch_pdf_query(const float *U, const float *L, int ldq, int64_t Q, 
     return hipGetLastError();
 }
 
-// Lane = candidate, block = 4 waves of 64 candidates x up to QG queries (blockIdx.y), the query
-// sums in LDS read as broadcasts.  Writes out[q][c] (pow domain, or root form with ROOT) and,
-// per query and wave, the smallest (bound, index) key of the wave's candidates.
+// Two candidates per lane (tiles 2v and 2v + 1 of wave v), block = 4 waves x up to QG queries
+// (blockIdx.y), the query sums in LDS read as broadcasts and shared by both candidates.  Writes
+// out[q][c] (pow domain, or root form with ROOT) and, per query and wave, the smallest (bound,
+// index) key of the wave's 128 candidates.
 template <int P, int QG, bool ROOT>
 __global__ __launch_bounds__(256) void k_pdf_scan(const float4 *__restrict__ pdf, int64_t N, int n,
                                                    const float *__restrict__ qpf, int64_t Q, float *__restrict__ out,
@@ -266,71 +267,94 @@ __global__ __launch_bounds__(256) void k_pdf_scan(const float4 *__restrict__ pdf
             q < Q ? reinterpret_cast<const float4 *>(qpf + q * kPdfQuery)[t % (kPdfQuery / 4)]
                   : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
-    const int64_t c = tile * 64 + lane;
-    const bool valid = c < N;
-    float x[kPdFine];
-    float sx = 0.f;  // sum of |P(x)_j|
+    const int64_t v = (int64_t)blockIdx.x * 4 + wave;  // this wave's index among the scan's waves
+    const int64_t tiles = (N + 63) / 64;
+    float x[2][kPdFine];
+    float sx[2] = {0.f, 0.f};  // sums of |P(x)_j|
+    int64_t c[2];
+    bool valid[2];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const float4 v = pdf[(tile * G + g) * 64 + lane];
-        x[4 * g] = v.x, x[4 * g + 1] = v.y, x[4 * g + 2] = v.z, x[4 * g + 3] = v.w;
-        sx += fabsf(v.x) + fabsf(v.y) + fabsf(v.z) + fabsf(v.w);
-    }
-    float inv[kPdFine];  // 1 / part size (an empty part has zero distance)
+    for (int h = 0; h < 2; ++h) {
+        const int64_t tile = 2 * v + h;
+        c[h] = tile * 64 + lane;
+        valid[h] = c[h] < N;
+        const int64_t tl = tile < tiles ? tile : 0;  // a tile past the end loads tile 0 (unused)
 #pragma unroll
-    for (int j = 0; j < kPdFine; ++j) {
-        int a, b;
-        pdf_part(n, j, a, b);
-        inv[j] = b > a ? 1.f / (float)(b - a) : 0.f;
+        for (int g = 0; g < G; ++g) {
+            const float4 w4 = pdf[(tl * G + g) * 64 + lane];
+            x[h][4 * g] = w4.x, x[h][4 * g + 1] = w4.y, x[h][4 * g + 2] = w4.z, x[h][4 * g + 3] = w4.w;
+            sx[h] += fabsf(w4.x) + fabsf(w4.y) + fabsf(w4.z) + fabsf(w4.w);
+        }
     }
+    // 1 / part size: every part but the last has floor(n/32) elements (an empty part has zero
+    // distance)
+    const int m = n / kPdFine;
+    const float inv_m = m > 0 ? 1.f / (float)m : 0.f;
+    const float inv_last = 1.f / (float)(n - (kPdFine - 1) * m);
     __syncthreads();
-#pragma unroll 2
+#pragma unroll 1
     for (int qq = 0; qq < QG; ++qq) {
         const int64_t q = q0 + qq;
         if (q >= Q) break;
         const float *sqf = reinterpret_cast<const float *>(sq[qq]);
-        float acc = 0.f;
+        float acc[2] = {0.f, 0.f};
 #pragma unroll
         for (int j = 0; j < kPdFine; ++j) {
-            const float d = x[j] - __builtin_amdgcn_fmed3f(x[j], sqf[kPdFine + j], sqf[j]);
-            if constexpr (P == 1) {
-                acc += fabsf(d);
-            } else {
-                // this part's margin: 4u (|P(x)_j| + |P(U)_j| + |P(L)_j|)
-                const float ds = fmaxf(fabsf(d) - fmaf(kPdfEps, fabsf(x[j]), sqf[2 * kPdFine + j]), 0.f);
-                if constexpr (P == 2)
-                    acc = fmaf(ds * inv[j], ds, acc);
-                else
-                    acc = fmaxf(acc, ds * inv[j]);
+            const float hi = sqf[j], lo = sqf[kPdFine + j];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float d = x[h][j] - __builtin_amdgcn_fmed3f(x[h][j], lo, hi);
+                if constexpr (P == 1) {
+                    acc[h] += fabsf(d);
+                } else {
+                    // this part's margin: 4u (|P(x)_j| + |P(U)_j| + |P(L)_j|)
+                    const float ds = fmaxf(fabsf(d) - fmaf(kPdfEps, fabsf(x[h][j]), sqf[2 * kPdFine + j]), 0.f);
+                    const float inv = j + 1 < kPdFine ? inv_m : inv_last;
+                    if constexpr (P == 2)
+                        acc[h] = fmaf(ds * inv, ds, acc[h]);
+                    else
+                        acc[h] = fmaxf(acc[h], ds * inv);
+                }
             }
         }
-        float f;
-        if constexpr (P == 1)
-            f = fmaxf(fmaf(acc, -64.f * 5.9604645e-8f, acc) - fmaf(kPdfEps, sx, sqf[3 * kPdFine]), 0.f);
-        else
-            f = acc * (1.f - 64.f * 5.9604645e-8f);
-        if (ROOT && P == 2) f = sqrtf(f) * (1.f - 4.f * 5.9604645e-8f);
-        if (valid) out[q * ldo + c] = f;
+        float f[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if constexpr (P == 1)
+                f[h] = fmaxf(fmaf(acc[h], -64.f * 5.9604645e-8f, acc[h]) - fmaf(kPdfEps, sx[h], sqf[3 * kPdFine]), 0.f);
+            else
+                f[h] = acc[h] * (1.f - 64.f * 5.9604645e-8f);
+            if (ROOT && P == 2) f[h] = sqrtf(f[h]) * (1.f - 4.f * 5.9604645e-8f);
+            if (valid[h]) out[q * ldo + c[h]] = f[h];
+        }
         if (wmin) {
-            // the wave's smallest bound, then its lowest lane (the smallest index among equals)
-            float m = valid ? f : kInf;
+            // the wave's smallest bound, then the smallest index holding it: the first tile's
+            // candidates precede the second's, and within a tile the lowest lane comes first
+            float m = fminf(valid[0] ? f[0] : kInf, valid[1] ? f[1] : kInf);
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
-            const unsigned long long ball = __ballot(valid && f == m);
-            if (lane == 0)
-                wmin[q * ldw + tile] = ball ? make_key(m, (int)(tile * 64 + __ffsll(ball) - 1 + cbase)) : kNoKey;
+            const unsigned long long b0 = __ballot(valid[0] && f[0] == m), b1 = __ballot(valid[1] && f[1] == m);
+            if (lane == 0) {
+                unsigned long long k = kNoKey;
+                if (b0)
+                    k = make_key(m, (int)(2 * v * 64 + __ffsll(b0) - 1 + cbase));
+                else if (b1)
+                    k = make_key(m, (int)((2 * v + 1) * 64 + __ffsll(b1) - 1 + cbase));
+                wmin[q * ldw + v] = k;
+            }
         }
     }
 }
+
+int64_t pdf_scan_waves(int64_t N) { return (N + 511) / 512 * 4; }
 
 template <int P, bool ROOT>
 static void pdf_scan_launch(const float4 *pdf, int64_t N, int n, const float *qpf, int64_t Q, float *out, int64_t ldo,
                             unsigned long long *wmin, int64_t cbase, hipStream_t s) {
     constexpr int QG = 16;
-    const dim3 grid((unsigned)((N + 255) / 256), (unsigned)((Q + QG - 1) / QG));
+    const dim3 grid((unsigned)((N + 511) / 512), (unsigned)((Q + QG - 1) / QG));
     hipLaunchKernelGGL((k_pdf_scan<P, QG, ROOT>), grid, dim3(256), 0, s, pdf, N, n, qpf, Q, out, ldo, wmin,
-                       pd_scan_waves(N), cbase);
+                       pdf_scan_waves(N), cbase);
 }
 
 hipError_t launch_pdf_scan(int p, const float4 *pdf, int64_t N, int n, const float *qpf, int64_t Q, float *out,
