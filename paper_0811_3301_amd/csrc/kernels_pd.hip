@@ -181,6 +181,23 @@ __device__ __forceinline__ void pdf_part(int n, int j, int &a, int &b) {
 
 constexpr float kPdfEps = 4.f * 5.9604645e-8f;  // 4u
 
+// Minimum of v over the wave, returned to every lane: DPP steps within quads, half-rows and rows,
+// then row broadcasts carry the minimum to lane 63, which is read back.  No LDS round trips.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_min_step(float v) {
+    const int o = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xf, false);
+    return fminf(v, __int_as_float(o));
+}
+__device__ __forceinline__ float wave_min(float v) {
+    v = dpp_min_step<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v = dpp_min_step<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+    v = dpp_min_step<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_min_step<0x140, 0xf>(v);  // row_mirror
+    v = dpp_min_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_min_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // pdf: [ceil(N/64)][kPdFine/4][64] float4 -- candidate 64t + l, parts 4g..4g+3 at [t][g][l].
 // One thread per (tile, group, lane); padding candidates get zeros.
 __global__ __launch_bounds__(256) void k_pdf_rows(const float *__restrict__ rows, int64_t N, int n,
@@ -292,7 +309,7 @@ __global__ __launch_bounds__(256) void k_pdf_scan(const float4 *__restrict__ pdf
     const float inv_m = m > 0 ? 1.f / (float)m : 0.f;
     const float inv_last = 1.f / (float)(n - (kPdFine - 1) * m);
     __syncthreads();
-#pragma unroll 1
+#pragma unroll 2
     for (int qq = 0; qq < QG; ++qq) {
         const int64_t q = q0 + qq;
         if (q >= Q) break;
@@ -330,9 +347,7 @@ __global__ __launch_bounds__(256) void k_pdf_scan(const float4 *__restrict__ pdf
         if (wmin) {
             // the wave's smallest bound, then the smallest index holding it: the first tile's
             // candidates precede the second's, and within a tile the lowest lane comes first
-            float m = fminf(valid[0] ? f[0] : kInf, valid[1] ? f[1] : kInf);
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) m = fminf(m, __shfl_xor(m, off));
+            const float m = wave_min(fminf(valid[0] ? f[0] : kInf, valid[1] ? f[1] : kInf));
             const unsigned long long b0 = __ballot(valid[0] && f[0] == m), b1 = __ballot(valid[1] && f[1] == m);
             if (lane == 0) {
                 unsigned long long k = kNoKey;
