@@ -117,6 +117,14 @@ void lbimp_ctx_destroy(lbimp_ctx *ctx);
  *                   prune almost as well as LB_Keogh;
  *   "pd_fine"       0/1 (default 0): lbimp_db_pd_bound evaluates the d = 32 cover of
  *                   "pd_prefilter" 2 instead of d = 8 (LBIMP_E_UNSUPPORTED for n < 64);
+ *   "dtw_split"     0/1 (default 0): the two-pass search runs the survivors' DTW (lane-per-pair
+ *                   kernel, w <= 63) in two row phases: rows [0, n/2) of every survivor, then
+ *                   rows [n/2, n) of the pairs still running there, repacked 64 to a wave (their
+ *                   band rows parked in device memory in between), so that waves whose pairs
+ *                   were mostly abandoned early do not run to the end;
+ *   "dtw_pool_slots" 0..2^26 (default 262,144): most pairs parked between the phases (about
+ *                   (2w + 3) x 4 bytes each, and at most an eighth of a "workspace_limit"); a
+ *                   pair finding the pool full finishes in the first phase;
  *   "workspace_limit" bytes (default 0, no bound): a search whose workspace would exceed it
  *                   splits the database into chunks of candidates (multiples of 2,048) searched
  *                   one after another, each through the whole path, the threshold carried from
@@ -259,8 +267,8 @@ int lbimp_nn_search_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t n
  * survivors' DTW group-per-pair, seeding DTW lane-per-pair, abandon bound with the LB_Keogh
  * tail, pass 0 with the piecewise-sum bound (the value of option "pd_prefilter": 0, 1 or 2),
  * early abandoning in LB_Improved, LB_Improved over survivor lists bucketed by candidate
- * range}.  Waits for the stream. */
-#define LBIMP_TUNE_KNOBS 9
+ * range, survivors' DTW in two row phases}.  Waits for the stream. */
+#define LBIMP_TUNE_KNOBS 10
 int lbimp_autotune(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, int64_t Q, int32_t w, int32_t p,
                    int32_t k, int32_t mode, int32_t *choice);
 

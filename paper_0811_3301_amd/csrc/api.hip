@@ -116,6 +116,8 @@ struct lbimp_ctx {
     bool pd_fine_bound = false;         // option "pd_fine": lbimp_db_pd_bound on the 32-part cover
     bool lbi_abandon = false;           // option "lbi_abandon"
     bool lbi_buckets = false;           // option "lbi_buckets"
+    bool dtw_split = false;             // option "dtw_split"
+    int64_t dtw_pool_slots = 1 << 18;   // option "dtw_pool_slots"
     size_t ws_limit = 0;                // option "workspace_limit" (bytes, 0: none)
     // ragged batches: stream pool, captured graph, pinned staging of the grouping metadata
     hipStream_t graph_stream = nullptr;
@@ -214,6 +216,7 @@ struct Knobs {
                         // its survivors; 2: 32-part cover, LB_Keogh inside the LB_Improved pass
     bool lbi_abandon = false;  // early abandoning inside the LB_Improved pass
     bool lbi_buckets = false;  // LB_Improved over bucketed survivor lists (XCD-local row reuse)
+    bool dtw_split = false;    // survivors' DTW in two row phases, the pairs still running repacked between
 };
 
 struct SearchSpec {  // Q queries of one length against one database
@@ -228,6 +231,7 @@ struct SearchSpec {  // Q queries of one length against one database
     const int64_t *kq = nullptr;  // device [Q] per-query k (each <= k), or nullptr: k for every query
     int ldo = 0;                  // output row stride in entries (0: k)
     size_t ws_limit = 0;          // workspace bound in bytes (0: none); the candidates are split into chunks to meet it
+    int64_t pool_slots = 1 << 18; // bound on the row-phase DTW's parked-pair slots
 };
 
 struct SearchDims {
@@ -239,6 +243,9 @@ struct SearchDims {
     size_t ring_bytes;  // strip-boundary scratch of the wide-band DTW
     bool brute, improved, from_minima, pd;
     bool fine;           // pass 0 on the 32-part cover, then LB_Improved with LB_Keogh fused (pd = 2)
+    bool split;          // survivors' DTW in two row phases (lane-per-pair kernel)
+    int split_row;       // first row of the second phase
+    int64_t pool_cap;    // parked-pair slots of the phases' pool
 };
 
 struct SearchBufs {
@@ -248,6 +255,8 @@ struct SearchBufs {
     long long *prefix, *tot;
     double *qpd;
     float *qpf;
+    float *pool;   // parked pairs of the row-phase DTW ([wb*2 + 3][pool_cap])
+    int *parkcnt;  // [Q] parked pairs per query, then the pool's slot counter
 };
 
 constexpr int64_t kChunkAlign = 2048;  // chunk sizes are multiples of the sweep's largest tile group
@@ -268,6 +277,15 @@ static void chunk_dims(const SearchSpec &sp, int64_t C, SearchDims &d) {
     const int64_t span = compact_wave_span();
     d.bs = std::max<int64_t>(span, ((int64_t)(2 << 20) / (4 * (int64_t)d.n)) / span * span);
     d.nb = (d.improved && sp.kn.lbi_buckets && d.C > d.bs && !d.fine) ? (int)((d.C + d.bs - 1) / d.bs) : 1;
+    // row phases: the second starts at half the series (a multiple of the kernel's row group);
+    // the pool holds up to a quarter of the chunk's pairs, at most the context's bound
+    const int lr = lane_rows(d.wb);
+    d.split_row = d.n / 2 / lr * lr;
+    d.pool_cap = std::min<int64_t>(sp.pool_slots, d.Q * d.C / 4);
+    if (sp.ws_limit)  // at most an eighth of a workspace bound
+        d.pool_cap = std::min<int64_t>(d.pool_cap, (int64_t)(sp.ws_limit / 8 / (sizeof(float) * (2 * d.wb + 3))));
+    d.split = sp.kn.dtw_split && d.improved && !sp.kn.dtw_group && d.wb <= kLaneMaxW && d.split_row >= lr &&
+              d.split_row < d.n - d.n % lr && d.pool_cap >= 64;
 }
 
 void layout(Carver &c, const SearchDims &d, SearchBufs &b);
@@ -328,6 +346,8 @@ void layout(Carver &c, const SearchDims &d, SearchBufs &b) {
     b.list0 = (d.pd && !d.fine && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
     b.qpd = (d.pd && !d.fine && any) ? c.take<double>((size_t)d.Q * 2 * kPdParts) : nullptr;
     b.qpf = (d.fine && any) ? c.take<float>((size_t)d.Q * kPdfQuery) : nullptr;
+    b.pool = (d.split && any) ? c.take<float>((size_t)(2 * d.wb + 3) * d.pool_cap) : nullptr;
+    b.parkcnt = (d.split && any) ? c.take<int>((size_t)d.Q + 1) : nullptr;
     b.list1 = (d.brute || !any) ? nullptr : c.take<int>((size_t)d.Q * d.C);
     b.list2 = (d.improved && any) ? c.take<int>((size_t)d.Q * d.C) : nullptr;
     b.counters = c.take<int>((size_t)d.Q * kCounters);  // cnt1, cnt2, rescnt, abandoned, cnt0 ([kCounters][Q])
@@ -500,9 +520,26 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
             stage_first(6);
             const bool dtw_ll = sp.kn.dtw_group && (wb <= kLaneMaxW || dtw_wavereg_wide_supported(n, wb));
             HIPTRY(launch_items_prefix(dl.cnt, 0, Q, dtw_batch(n, wb, dtw_ll), b.prefix, s));
-            HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
-                              k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, dtw_ll,
-                              b.ring, d.ring_bytes, sp.kn.cascade ? S1v : nullptr, d.Np, s));
+            if (d.split) {
+                // rows [0, R) of every survivor, parking the pairs still running in the pool (their
+                // slots listed per query in list1, free once LB_Improved has read it); then rows
+                // [R, n) of the parked pairs, repacked 64 to a wave
+                HIPTRY(launch_fill_i32(b.parkcnt, 0, Q + 1, s));
+                const DtwPhase ph0{0, d.split_row, false, b.pool, d.pool_cap, b.parkcnt + Q, b.list1, d.C, b.parkcnt};
+                HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
+                                  k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, false,
+                                  b.ring, d.ring_bytes, sp.kn.cascade ? S1v : nullptr, d.Np, s, &ph0));
+                HIPTRY(launch_items_prefix(b.parkcnt, 0, Q, dtw_batch(n, wb, false), b.prefix, s));
+                const DtwPhase ph1{d.split_row, 0, true, b.pool, d.pool_cap, nullptr, nullptr, 0, nullptr};
+                HIPTRY(launch_dtw(p, db->rows, n, wb, qd, PairList{b.list1, d.C, b.parkcnt, 0}, b.prefix, Q, nullptr,
+                                  grid, k == 1 ? b.best : nullptr, k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt,
+                                  abandoned, nullptr, true, false, b.ring, d.ring_bytes,
+                                  sp.kn.cascade ? S1v : nullptr, d.Np, s, &ph1));
+            } else {
+                HIPTRY(launch_dtw(p, db->rows, n, wb, qd, dl, b.prefix, Q, nullptr, grid, k == 1 ? b.best : nullptr,
+                                  k == 1 ? nullptr : b.thr, b.res, d.ldres, rescnt, abandoned, nullptr, true, dtw_ll,
+                                  b.ring, d.ring_bytes, sp.kn.cascade ? S1v : nullptr, d.Np, s));
+            }
         }
         if (chunked && c1 < N) {  // the next chunk starts from the k best keys so far
             if (k > 1) HIPTRY(launch_res_shrink(b.res, d.ldres, rescnt, Q, k, sp.kq, b.thr, s));
@@ -522,6 +559,7 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
 static Knobs ctx_knobs(const lbimp_ctx *ctx) {
     Knobs k{ctx->seeds, ctx->lbi_pipeline, ctx->sweep_shape, false, false, true, ctx->pd_prefilter, ctx->lbi_abandon};
     k.lbi_buckets = ctx->lbi_buckets;
+    k.dtw_split = ctx->dtw_split;
     return k;
 }
 
@@ -532,12 +570,13 @@ static TuneKey tune_key(const lbimp_db *db, int64_t Q, int wb, int p, int k, int
 static Knobs knobs_of(const std::array<int, kTuneKnobs> &v) {
     Knobs k{v[0], v[2], v[1], v[3] != 0, v[4] != 0, v[5] != 0, v[6], v[7] != 0};
     k.lbi_buckets = v[8] != 0;
+    k.dtw_split = v[9] != 0;
     return k;
 }
 
 static std::array<int, kTuneKnobs> knob_values(const Knobs &k) {
     return {k.seeds, k.sweep_shape, k.lbi_pipeline, k.dtw_group ? 1 : 0, k.seed_lane ? 1 : 0,
-            k.cascade ? 1 : 0, k.pd, k.lbi_abandon ? 1 : 0, k.lbi_buckets ? 1 : 0};
+            k.cascade ? 1 : 0, k.pd, k.lbi_abandon ? 1 : 0, k.lbi_buckets ? 1 : 0, k.dtw_split ? 1 : 0};
 }
 
 // The tuned choice for this batch shape if there is one, else the context's options.
@@ -570,7 +609,9 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
                     SearchSpec sp{db, nullptr, Q, wb, p, k, mode, nullptr, nullptr, nullptr,
                                   Knobs{sd, 1, sh, false, false, true, pdv}};
                     sp.kn.lbi_buckets = bk;
+                    sp.kn.dtw_split = true;  // the largest layout: with the row-phase pool
                     sp.ws_limit = ctx->ws_limit;
+                    sp.pool_slots = ctx->dtw_pool_slots;
                     SearchDims d;
                     if (int r = dims_of(sp, ctx->num_cu, d)) return r;
                     SearchBufs b;
@@ -612,6 +653,7 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
     auto time_of = [&](const Knobs &kn, float *ms) -> int {
         SearchSpec sp{db, queries, Q, wb, p, k, mode, idx, dist, nullptr, kn};
         sp.ws_limit = ctx->ws_limit;
+        sp.pool_slots = ctx->dtw_pool_slots;
         SearchDims d;
         if (int r = dims_of(sp, ctx->num_cu, d)) return r;
         SearchBufs b;
@@ -706,6 +748,12 @@ static int tune_search(lbimp_ctx *ctx, const lbimp_db *db, const float *qdev, co
                 if (int r = consider(kn)) return r;
             }
         }
+    }
+    if (improved && wb <= kLaneMaxW && !best.dtw_group) {
+        // two row phases for the survivors' DTW, repacking the pairs still running at half the series
+        Knobs kn = best;
+        kn.dtw_split = !kn.dtw_split;
+        if (int r = consider(kn)) return r;
     }
     ctx->tuned[tune_key(db, Q, wb, p, k, mode)] = knob_values(best);
     *out = best;
@@ -850,6 +898,7 @@ static int plan_ragged(lbimp_ctx *ctx, const lbimp_db *const *dbs, int32_t ndb, 
                       knobs_for(ctx, db, Qg, kv.first.second, p, kg, mode)};
         sp.ldo = plan.kmax;
         sp.ws_limit = ctx->ws_limit;
+        sp.pool_slots = ctx->dtw_pool_slots;
         plan.specs.push_back(sp);
         if (int r = dims_of(plan.specs.back(), ctx->num_cu, plan.dims[plan.specs.size() - 1])) return r;
         plan.meta_elems += 3 * (size_t)Qg;
@@ -943,6 +992,11 @@ int lbimp_ctx_set_option(lbimp_ctx *ctx, const char *name, int64_t value) {
         ctx->pd_prefilter = (int)value;
     } else if (!strcmp(name, "pd_fine")) {
         ctx->pd_fine_bound = value != 0;
+    } else if (!strcmp(name, "dtw_split")) {
+        ctx->dtw_split = value != 0;
+    } else if (!strcmp(name, "dtw_pool_slots")) {
+        if (value < 0 || value > (int64_t)1 << 26) return fail(LBIMP_E_INVALID, "dtw_pool_slots must be in [0, 2^26]");
+        ctx->dtw_pool_slots = value;
     } else if (!strcmp(name, "lbi_abandon")) {
         ctx->lbi_abandon = value != 0;
     } else if (!strcmp(name, "lbi_buckets")) {
@@ -1227,6 +1281,7 @@ int lbimp_nn_search(lbimp_ctx *ctx, const lbimp_db *db, const float *queries, in
     }
     SearchSpec sp{db, queries, Q, w, p, k, mode, idx, dist, nullptr, knobs_for(ctx, db, Q, wb, p, k, mode)};
     sp.ws_limit = ctx->ws_limit;
+    sp.pool_slots = ctx->dtw_pool_slots;
     SearchDims d;
     if (int r = dims_of(sp, ctx->num_cu, d)) return r;
     SearchBufs bufs;
@@ -1270,6 +1325,7 @@ int lbimp_nn_search_noalloc(lbimp_ctx *ctx, const lbimp_db *db, const float *que
     // the candidates are split into chunks small enough for the scratch (or the context's bound)
     sp.ws_limit = ctx->ws_limit ? std::min<size_t>(ctx->ws_limit, LBIMP_NOALLOC_SCRATCH_BYTES)
                                 : (size_t)LBIMP_NOALLOC_SCRATCH_BYTES;
+    sp.pool_slots = ctx->dtw_pool_slots;
     SearchDims d;
     if (int r = dims_of(sp, ctx->num_cu, d)) return r;
     SearchBufs bufs;

@@ -191,6 +191,20 @@ struct DtwArgs {
     const u64 *tkeys;  // [Q] abandon thresholds: best (k = 1) or thr (k > 1); always a valid array
     const float *S1;   // [Q][ldS] LB_Keogh^p of every pair (tightens the abandon bound), or nullptr
     int64_t ldS;
+    // Row phases (lane-per-pair kernel only).  With row1 > 0 the launch runs rows [row0, row1)
+    // and parks every pair still running there: its band row, LB_Keogh sum so far and candidate
+    // go to slot s of `pool` (field f at pool[f * pool_cap + s], slots from the counter
+    // *pool_ctr) and s is appended to park_list[q][*] (counts park_cnt[q]); a pair finding the
+    // pool full runs on to the end.  With resume the pairs of pl are such slots, and the launch
+    // continues them from row0.  row0 and row1 are multiples of the kernel's row group.
+    int row0 = 0, row1 = 0;
+    bool resume = false;
+    float *pool = nullptr;
+    int64_t pool_cap = 0;
+    int *pool_ctr = nullptr;
+    int *park_list = nullptr;
+    int64_t ld_park = 0;
+    int *park_cnt = nullptr;
 };
 
 // Lower bound of a pair's DTW_p once rows 0..i are done: the minimum of row i plus the

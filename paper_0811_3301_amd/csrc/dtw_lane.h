@@ -57,9 +57,10 @@ __device__ __forceinline__ void dtw_rowsR(float (&D)[2 * W + 1], const float (&x
     }
 }
 
-constexpr int lane_rows(int w) { return w <= 32 ? 8 : w <= 53 ? 6 : 4; }
 
-template <int P, int W, bool CASCADE>
+// PH: row phases (DtwArgs::row0/row1/resume) compiled in; without them the kernel keeps the
+// registers (and waves per SIMD) of a plain sweep over all rows.
+template <int P, int W, bool CASCADE, bool PH>
 __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
     constexpr int BW = 2 * W + 1;
     constexpr int kLaneRows = lane_rows(W);
@@ -90,53 +91,91 @@ __global__ __launch_bounds__(64) void k_dtw_lane(DtwArgs a) {
             cur_q = q;
         }
         const long long jj = b * 64 + lane;
-        const int cl = jj < pair_count(a.pl, q, items.bk) ? pair_cand(a.pl, q, jj, items.bk) : -1;
-        bool active = cl >= 0;
-        const int c = active ? cl : 0;
-        const float *x = a.rows + (int64_t)c * n;
+        const int e = jj < pair_count(a.pl, q, items.bk) ? pair_cand(a.pl, q, jj, items.bk) : -1;
+        bool active = e >= 0;
         float D[BW];
+        float done = 0.f;  // LB_Keogh^p terms of the rows already computed
+        int c;
+        if (PH && a.resume) {  // e is the pool slot of a pair parked by the previous launch
+            const int64_t sl = active ? e : 0;
+            c = active ? reinterpret_cast<const int *>(a.pool)[(int64_t)(BW + 1) * a.pool_cap + sl] : 0;
 #pragma unroll
-        for (int k = 0; k < BW; ++k) D[k] = (k == W) ? 0.f : kInf;
+            for (int k = 0; k < BW; ++k) D[k] = active ? a.pool[(int64_t)k * a.pool_cap + sl] : kInf;
+            done = active ? a.pool[(int64_t)BW * a.pool_cap + sl] : 0.f;
+        } else {
+            c = active ? e : 0;
+#pragma unroll
+            for (int k = 0; k < BW; ++k) D[k] = (k == W) ? 0.f : kInf;
+        }
+        const float *x = a.rows + (int64_t)c * n;
         int stopped = 0;
         const int nfull = n - n % kLaneRows;
+        // rows [a.row0, rpark) first; at rpark (< nfull) the running pairs are parked
+        const int rpark = (PH && a.row1 > 0 && a.row1 < nfull) ? a.row1 : nfull;
         float xs[kLaneRows];
-        if (nfull > 0) {
-#pragma unroll
-            for (int r = 0; r < kLaneRows; ++r) xs[r] = x[r];
-        }
-        int i0 = 0;
+        int i0 = PH ? a.row0 : 0;
         // The threshold used after each group of rows is loaded one group ahead, from one pointer
         // with no branch around the load, so the wait for it lands where it is used.
         const u64 *tq = a.tkeys + q;
         u64 tcur = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         float s1v = 0.f;
         if constexpr (cascade) s1v = active ? a.S1[q * a.ldS + c] : 0.f;  // S1 may be a chunk's shifted base
-        float done = 0.f;  // LB_Keogh^p terms of the rows already computed
-        for (; i0 < nfull; i0 += kLaneRows) {
-            float xn[kLaneRows];
-            const int inext = i0 + kLaneRows < nfull ? i0 + kLaneRows : i0;  // prefetch the next rows
+        int stop_at = rpark;
+        for (int round = 0; round < 2; ++round) {
+            if (i0 < stop_at) {
 #pragma unroll
-            for (int r = 0; r < kLaneRows; ++r) xn[r] = x[inext + r];
-            const u64 tnext = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            dtw_rowsR<P, W, kLaneRows>(D, xs, ypad + i0);
-            if constexpr (cascade) {
-#pragma unroll
-                for (int r = 0; r < kLaneRows; ++r) done += lbk_term<P>(xs[r], sL[i0 + r], sU[i0 + r]);
+                for (int r = 0; r < kLaneRows; ++r) xs[r] = x[i0 + r];
             }
+            for (; i0 < stop_at; i0 += kLaneRows) {
+                float xn[kLaneRows];
+                const int inext = i0 + kLaneRows < stop_at ? i0 + kLaneRows : i0;  // prefetch the next rows
 #pragma unroll
-            for (int r = 0; r < kLaneRows; ++r) xs[r] = xn[r];
-            if (a.abandon) {
-                float mn = D[0];
+                for (int r = 0; r < kLaneRows; ++r) xn[r] = x[inext + r];
+                const u64 tnext = __hip_atomic_load(tq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                dtw_rowsR<P, W, kLaneRows>(D, xs, ypad + i0);
+                if constexpr (cascade) {
 #pragma unroll
-                for (int k = 1; k < BW; ++k) mn = fminf(mn, D[k]);
-                if constexpr (cascade) mn = cascade_bound(mn, s1v, done, shrink);
-                if (active && make_key(mn, c) >= tcur) {
-                    active = false;
-                    ++stopped;
+                    for (int r = 0; r < kLaneRows; ++r) done += lbk_term<P>(xs[r], sL[i0 + r], sU[i0 + r]);
                 }
-                tcur = tnext;
-                if (!__any(active)) break;
+#pragma unroll
+                for (int r = 0; r < kLaneRows; ++r) xs[r] = xn[r];
+                if (a.abandon) {
+                    float mn = D[0];
+#pragma unroll
+                    for (int k = 1; k < BW; ++k) mn = fminf(mn, D[k]);
+                    if constexpr (cascade) mn = cascade_bound(mn, s1v, done, shrink);
+                    if (active && make_key(mn, c) >= tcur) {
+                        active = false;
+                        ++stopped;
+                    }
+                    tcur = tnext;
+                    if (!__any(active)) break;
+                }
             }
+            if (!PH || round > 0 || stop_at >= nfull || i0 < stop_at) break;
+            // park the running pairs in wave-contiguous pool slots; those past the pool's end run on
+            const u64 m = __ballot(active);
+            int base = 0;
+            if (lane == 0 && m) base = atomicAdd(a.pool_ctr, __popcll(m));
+            base = __shfl(base, 0);
+            const int64_t slot = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
+            const bool fits = active && slot < a.pool_cap;
+            if (fits) {
+#pragma unroll
+                for (int k = 0; k < BW; ++k) a.pool[(int64_t)k * a.pool_cap + slot] = D[k];
+                a.pool[(int64_t)BW * a.pool_cap + slot] = done;
+                reinterpret_cast<int *>(a.pool)[(int64_t)(BW + 1) * a.pool_cap + slot] = c;
+            }
+            const u64 mf = __ballot(fits);
+            if (mf) {
+                int pos = 0;
+                if (lane == 0) pos = atomicAdd(&a.park_cnt[q], __popcll(mf));
+                pos = __shfl(pos, 0);
+                if (fits) a.park_list[q * a.ld_park + pos + __popcll(mf & ((1ull << lane) - 1ull))] = (int)slot;
+            }
+            active = active && !fits;
+            if (!__any(active)) break;
+            stop_at = nfull;  // the pairs that found no slot finish here
         }
         if (i0 >= nfull)
             for (int i = nfull; i < n; ++i) dtw_row<P, W>(D, x[i], ypad + i);
@@ -157,15 +196,24 @@ static void dtw_lane_launch(int num_cu, const DtwArgs &a_in, hipStream_t s) {
     if (a.S1 && lds_of(true) > kLdsBudget) a.S1 = nullptr;  // no room for U, L: row minimum only
     if constexpr (P == kPInf) a.S1 = nullptr;               // the LB_Keogh tail bound sums p-th powers
     const size_t lds = lds_of(a.S1 != nullptr);
+    const bool ph = a.row1 > 0 || a.resume;
+#define LBIMP_DTW_LANE(CC, PP)                                                                                         \
+    hipLaunchKernelGGL((k_dtw_lane<P, W, CC, PP>), dim3(persistent_grid(k_dtw_lane<P, W, CC, PP>, lds, num_cu)), \
+                       dim3(64), lds, s, a)
     if constexpr (P != kPInf) {
         if (a.S1) {
-            hipLaunchKernelGGL((k_dtw_lane<P, W, true>), dim3(persistent_grid(k_dtw_lane<P, W, true>, lds, num_cu)),
-                               dim3(64), lds, s, a);
+            if (ph)
+                LBIMP_DTW_LANE(true, true);
+            else
+                LBIMP_DTW_LANE(true, false);
             return;
         }
     }
-    hipLaunchKernelGGL((k_dtw_lane<P, W, false>), dim3(persistent_grid(k_dtw_lane<P, W, false>, lds, num_cu)),
-                       dim3(64), lds, s, a);
+    if (ph)
+        LBIMP_DTW_LANE(false, true);
+    else
+        LBIMP_DTW_LANE(false, false);
+#undef LBIMP_DTW_LANE
 }
 
 using DtwLaneFn = void (*)(int, const DtwArgs &, hipStream_t);

@@ -15,6 +15,8 @@ constexpr float kInf = __builtin_huge_valf();
 constexpr unsigned long long kNoKey = ~0ull;  // larger than every (distance, index) key
 constexpr size_t kLdsBudget = 65536;          // dynamic LDS per workgroup used by any kernel
 constexpr int kLaneMaxW = 63;                 // widest band (half-width) of the lane-per-pair DTW
+// rows per group of the lane-per-pair DTW (its unit of early abandoning and of row phases)
+constexpr int lane_rows(int w) { return w <= 32 ? 8 : w <= 53 ? 6 : 4; }
 constexpr int kLbiRegMaxW = 52;               // widest band of the register-state LB_Improved
 constexpr int kCounters = 5;                  // per-query counters of a search: cnt1, cnt2, rescnt, abandoned, cnt0
 constexpr int kPdParts = 8;                   // parts d of the piecewise-sum cover (Sec. 9)
@@ -161,11 +163,22 @@ hipError_t launch_lbk_gather(int p, const float *rows, int n, QueryData qd, Pair
 int dtw_batch(int n, int w, bool low_latency);
 bool dtw_wavereg_wide_supported(int n, int w);  // group-per-pair kernel for 63 < w (low_latency)
 size_t dtw_strip_scratch(int p, int n, int w, int num_cu);
+// Row phases of the lane-per-pair DTW (w <= kLaneMaxW, not low_latency): see DtwArgs.
+struct DtwPhase {
+    int row0, row1;
+    bool resume;
+    float *pool;
+    int64_t pool_cap;
+    int *pool_ctr;
+    int *park_list;
+    int64_t ld_park;
+    int *park_cnt;
+};
 hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, PairList pl, const long long *prefix,
                       int64_t Q, int *ctr, int num_cu, unsigned long long *best, const unsigned long long *thr,
                       unsigned long long *res, int64_t ldres, int *rescnt, int *abandoned, float *out_root,
                       bool abandon, bool low_latency, float *ring, size_t ring_bytes, const float *S1,
-                      int64_t ldS, hipStream_t s);
+                      int64_t ldS, hipStream_t s, const DtwPhase *ph = nullptr);
 
 // k-th smallest key of res[q][0..min(rescnt[q], 64)) into thr[q] (kNoKey if fewer than k), with
 // k = kq[q] when kq (device [Q]) is given.

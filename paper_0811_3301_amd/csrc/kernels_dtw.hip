@@ -233,12 +233,24 @@ hipError_t launch_dtw(int p, const float *rows, int n, int w, QueryData qd, Pair
                       int64_t Q, int *ctr, int num_cu, unsigned long long *best, const unsigned long long *thr,
                       unsigned long long *res, int64_t ldres, int *rescnt, int *abandoned, float *out_root,
                       bool abandon, bool low_latency, float *ring, size_t ring_bytes, const float *S1,
-                      int64_t ldS, hipStream_t s) {
+                      int64_t ldS, hipStream_t s, const DtwPhase *ph) {
+    if (ph && (w > kLaneMaxW || low_latency)) return hipErrorInvalidValue;  // phases: lane-per-pair kernel only
     if (w <= kLaneMaxW || !low_latency || dtw_wavereg_wide_supported(n, w)) {
         const u64 *tkeys = best ? best : thr;
         if (!tkeys) return hipErrorInvalidValue;  // callers pass a threshold array, kNoKey-filled if unused
         DtwArgs a{rows, n, qd, pl, prefix, Q, ctr, best, thr, res, ldres, rescnt, abandoned, out_root, abandon, tkeys,
                   abandon && p != kPInf ? S1 : nullptr, ldS};  // the LB_Keogh tail bound sums p-th powers
+        if (ph) {
+            a.row0 = ph->row0;
+            a.row1 = ph->row1;
+            a.resume = ph->resume;
+            a.pool = ph->pool;
+            a.pool_cap = ph->pool_cap;
+            a.pool_ctr = ph->pool_ctr;
+            a.park_list = ph->park_list;
+            a.ld_park = ph->ld_park;
+            a.park_cnt = ph->park_cnt;
+        }
         if (w > kLaneMaxW && low_latency) return launch_dtw_wavereg_wide(p, w, num_cu, a, s);
         if (w > kLaneMaxW) return launch_dtw_strip(p, w, num_cu, a, ring, ring_bytes, s);
         if (low_latency) return launch_dtw_wavereg(p, w, num_cu, a, s);

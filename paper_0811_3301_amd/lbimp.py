@@ -68,7 +68,7 @@ SIGNATURES = {
     "lbimp_ctx_copy_tuning": (ctypes.c_int, [_vp, _vp]),
 }
 TUNE_KNOBS = ("seeds", "sweep_shape", "lbi_pipeline", "dtw_group", "seed_lane", "cascade", "pd", "lbi_abandon",
-              "lbi_buckets")
+              "lbi_buckets", "dtw_split")
 
 _lib = None
 

@@ -144,6 +144,8 @@ static void chunked_and_noalloc() {
                         OK(lbimp_ctx_set_option(ctx, "pd_prefilter", pd));
                         OK(lbimp_ctx_set_option(ctx, "lbi_buckets", ((p & 3) + pd + k) & 1));
                         OK(lbimp_ctx_set_option(ctx, "lbi_pipeline", ((p & 3) + mode) & 1));
+                        OK(lbimp_ctx_set_option(ctx, "dtw_split", (mode + k + pd) & 1));
+                        OK(lbimp_ctx_set_option(ctx, "dtw_pool_slots", pd == 1 ? 64 : 1 << 18));
                         OK(lbimp_nn_search(ctx, db, qs, Q, 13, p, k, mode, idx, dist, st.data()));
                         check_stats(st, Q, N, "chunked");
                         const long long a0 = hip_stub_allocations();
@@ -202,6 +204,7 @@ static void invalid_arguments() {
     CHECK(lbimp_ctx_set_option(ctx, "workspace_limit", -1) == LBIMP_E_INVALID, "negative bound accepted");
     CHECK(lbimp_ctx_set_option(ctx, "seeds", 65) == LBIMP_E_INVALID, "65 seeds accepted");
     CHECK(lbimp_ctx_set_option(ctx, "pd_prefilter", 3) == LBIMP_E_INVALID, "pass-0 form 3 accepted");
+    CHECK(lbimp_ctx_set_option(ctx, "dtw_pool_slots", -1) == LBIMP_E_INVALID, "negative pool accepted");
     OK(lbimp_ctx_set_option(ctx, "pd_fine", 1));
     CHECK(lbimp_db_pd_bound(ctx, db, x, x, 1, 1, dev<float>(100)) == LBIMP_E_UNSUPPORTED,
           "fine cover accepted for n = 10");

@@ -29,7 +29,7 @@ def test_autotune_choice_keeps_results(L, n, w, mode, k):
         choice = L.lbimp_autotune(ctx, db, Yd, w, 1, k, mode)
         assert choice["seeds"] in (8, 16, 32, 64) and 0 <= choice["sweep_shape"] <= 5
         assert all(choice[key] in (0, 1) for key in ("lbi_pipeline", "dtw_group", "seed_lane", "cascade",
-                                                             "lbi_abandon", "lbi_buckets"))
+                                                             "lbi_abandon", "lbi_buckets", "dtw_split"))
         assert choice["pd"] in (0, 1, 2)
         got_i, got_d, got_s = L.lbimp_nn_search(ctx, db, Yd, w, 1, k, mode)  # runs with the tuned choice
         assert torch.equal(ref_i, got_i)

@@ -298,6 +298,54 @@ def test_nn_search_pd_prefilter(L, ctx, mode, p, k, n, w, pd):
     db.close()
 
 
+@pytest.mark.parametrize("n,w", [(20, 3), (64, 6), (128, 13), (256, 26), (300, 45), (512, 51), (200, 63)])
+@pytest.mark.parametrize("p,k", [(1, 1), (2, 3), (INF, 2)])
+@pytest.mark.parametrize("slots,pd", [(1 << 18, 0), (64, 0), (1 << 18, 2)])
+def test_nn_search_dtw_split(L, ctx, n, w, p, k, slots, pd):
+    """The survivors' DTW in two row phases (pairs still running at half the series parked and
+    repacked): the same answers, bit for bit, as one phase, matching the oracle; a pool of 64
+    slots overflows, and the pairs without a slot finish in the first phase."""
+    _say(f"nn_search dtw_split n={n} w={w} p={p} k={k} slots={slots} pd={pd}")
+    X = walks(3000, n, 60)
+    Ys = walks(9, n, 61)
+    db = L.Db(ctx, to_dev(X))
+    Yd = to_dev(Ys)
+    L.lbimp_ctx_set_option(ctx, "pd_prefilter", pd)
+    try:
+        ri, rd, _ = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
+        L.lbimp_ctx_set_option(ctx, "dtw_split", 1)
+        L.lbimp_ctx_set_option(ctx, "dtw_pool_slots", slots)
+        idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
+    finally:
+        L.lbimp_ctx_set_option(ctx, "dtw_split", 0)
+        L.lbimp_ctx_set_option(ctx, "dtw_pool_slots", 1 << 18)
+        L.lbimp_ctx_set_option(ctx, "pd_prefilter", 0)
+    assert torch.equal(idx, ri) and torch.equal(dist, rd)
+    check_knn(X, Ys[:4], w, p, k, idx.cpu().numpy()[:4], dist.cpu().numpy()[:4], f"split n={n} w={w} p={p}")
+    check_stats(X, Ys, w, p, st, "improved", pd=bool(pd), pd_parts=fine_parts(pd, "improved", n, w))
+    db.close()
+
+
+def test_nn_search_dtw_split_chunked(L, ctx):
+    """Row phases in every chunk of a bounded workspace (the pool capped by the bound)."""
+    X = walks(9_000, 64, 62)
+    Ys = walks(6, 64, 63)
+    db = L.Db(ctx, to_dev(X))
+    Yd = to_dev(Ys)
+    ri, rd, _ = L.lbimp_nn_search(ctx, db, Yd, 6, 1, 2, "improved")
+    small = L.Ctx(0)
+    try:
+        L.lbimp_ctx_set_option(small, "dtw_split", 1)
+        L.lbimp_ctx_set_option(small, "workspace_limit", 400_000)
+        idx, dist, st = L.lbimp_nn_search(small, db, Yd, 6, 1, 2, "improved")
+        torch.cuda.synchronize()
+    finally:
+        small.close()
+    assert torch.equal(idx, ri) and torch.equal(dist, rd)
+    check_knn(X, Ys, 6, 1, 2, idx.cpu().numpy(), dist.cpu().numpy(), "split chunked")
+    db.close()
+
+
 @pytest.mark.parametrize("n,w", [(128, 13), (256, 26), (300, 80), (512, 102), (2300, 600)])
 @pytest.mark.parametrize("p,k", [(1, 1), (2, 3), (INF, 1)])
 def test_nn_search_lbi_abandon(L, ctx, n, w, p, k):
