@@ -105,8 +105,9 @@ __device__ __forceinline__ void lbi_forward(float &acc, float &s1, const float (
                 gx = fmaxf(gx, x);
                 gn = fminf(gn, x);
                 if (!FIRST || o >= W) {  // in the first block, windows of o < W start before the series
-                    const float um = fmaxf(hx[o + 1], gx);
-                    const float lm = fminf(hn[o + 1], gn);
+                    // the first block's windows start at position 0: the running max/min alone
+                    const float um = FIRST ? gx : fmaxf(hx[o + 1], gx);
+                    const float lm = FIRST ? gn : fminf(hn[o + 1], gn);
                     const float yo = f4get<t>(yv[g & 1]);
                     const float d = yo - __builtin_amdgcn_fmed3f(yo, lm, um);
                     acc = pacc<P>(acc, d);
@@ -245,8 +246,14 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
                 const int dst = dst_of(lane);
                 const bool tail = e0 + lane >= n;
                 const float lo = (!F || tail) ? l : -kInf, hi = (!F || tail) ? u : kInf;
+                if (F && e0 + SPAN <= n) {  // uniform: no position past the series, the raw row is staged as is
 #pragma unroll
-                for (int t = 0; t < (D >= 1 ? 64 : 1); ++t) stage[t * S + dst] = __builtin_amdgcn_fmed3f(v[t], lo, hi);
+                    for (int t = 0; t < (D >= 1 ? 64 : 1); ++t) stage[t * S + dst] = v[t];
+                } else {
+#pragma unroll
+                    for (int t = 0; t < (D >= 1 ? 64 : 1); ++t)
+                        stage[t * S + dst] = __builtin_amdgcn_fmed3f(v[t], lo, hi);
+                }
                 ys[dst] = sY[min(max(e0 + lane - W, 0), n - 1)];
                 if constexpr (F) {
                     us[dst] = tail ? kInf : u;
