@@ -369,9 +369,10 @@ hipError_t launch_lbk_sweep(int p, int shape, const float4 *il, int64_t N, int n
 // ------------------------------------------------------------------ seed selection
 // Threshold seeding: the paper's scan starts from b = inf and tightens b in database order;
 // a parallel pass instead computes the DTW of the candidates with the smallest LB_Keogh first.
-// Each thread keeps its 4 smallest (value, index) keys; the 1024 keys of the block are sorted
-// bitonically in LDS and the first S taken.  Approximate top-S is enough: any threshold that
-// is the DTW of some candidate is a valid (never too small) best-so-far.
+// Each thread keeps its 4 smallest (value, index) keys; of the 1024 keys of the block one wave
+// then takes the S with the smallest values (a radix select on the value bits, ties at the S-th
+// value taken in key position order).  Approximate top-S is enough: any threshold that is the
+// DTW of some candidate is a valid (never too small) best-so-far.
 template <bool FROM_KEYS>
 __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, int64_t ldS, int64_t cstart, int64_t N,
                                                        const unsigned long long *__restrict__ wmin, int64_t nw,
@@ -415,26 +416,44 @@ __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, in
 #pragma unroll
     for (int a = 0; a < 4; ++a) keys[threadIdx.x * 4 + a] = top[a];
     __syncthreads();
-    for (int size = 2; size <= 1024; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < 512; t += 256) {
-                int i = 2 * t - (t & (stride - 1));
-                int j = i + stride;
-                bool up = (i & size) == 0;
-                unsigned long long a = keys[i], b = keys[j];
-                if ((a > b) == up) {
-                    keys[i] = b;
-                    keys[j] = a;
-                }
-            }
-            __syncthreads();
-        }
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    unsigned long long kv[16];
+    unsigned hv[16];  // the value half of each key (values are >= 0, so their bits order them)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        kv[j] = keys[j * 64 + lane];
+        hv[j] = (unsigned)(kv[j] >> 32);
     }
-    for (int r = threadIdx.x; r < S; r += 256) {
-        unsigned long long k = keys[r];
-        int c = k == kNoKey ? -1 : (int)(k & 0xffffffffu);
-        seeds[q * S + r] = c;
-        if (c >= 0) row[c] = kInf;  // its DTW is computed by the seeding stage
+    // T = the S-th smallest value: the largest T with fewer than S values below it, bit by bit
+    unsigned T = 0;
+    for (int b = 31; b >= 0; --b) {
+        const unsigned cand = T | (1u << b);
+        int below = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) below += __popcll(__ballot(hv[j] < cand));
+        if (below < S) T = cand;
+    }
+    // every key below T, then keys equal to T in position order until there are S (the 1024 keys
+    // hold at least S at or below T, so exactly S are written)
+    int nlt = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) nlt += __popcll(__ballot(hv[j] < T));
+    const unsigned long long lower = (1ull << lane) - 1ull;
+    int lt = 0, eq = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const unsigned long long mlt = __ballot(hv[j] < T), meq = __ballot(hv[j] == T);
+        int r = -1;
+        if (hv[j] < T) r = lt + __popcll(mlt & lower);
+        else if (hv[j] == T && eq + __popcll(meq & lower) < S - nlt) r = nlt + eq + __popcll(meq & lower);
+        if (r >= 0) {
+            const int c = kv[j] == kNoKey ? -1 : (int)(kv[j] & 0xffffffffu);
+            seeds[q * S + r] = c;
+            if (c >= 0) row[c] = kInf;  // its DTW is computed by the seeding stage
+        }
+        lt += __popcll(mlt);
+        eq += __popcll(meq);
     }
 }
 
