@@ -369,9 +369,9 @@ hipError_t launch_lbk_sweep(int p, int shape, const float4 *il, int64_t N, int n
 // ------------------------------------------------------------------ seed selection
 // Threshold seeding: the paper's scan starts from b = inf and tightens b in database order;
 // a parallel pass instead computes the DTW of the candidates with the smallest LB_Keogh first.
-// Each thread keeps its 4 smallest (value, index) keys; of the 1024 keys of the block one wave
-// then takes the S with the smallest values (a radix select on the value bits, ties at the S-th
-// value taken in key position order).  Approximate top-S is enough: any threshold that is the
+// Each thread keeps its 4 smallest (value, index) keys of a contiguous range of entries; of the
+// 1024 keys of the block one wave then takes the S with the smallest values (a radix select on
+// the value bits).  Approximate top-S is enough: any threshold that is the
 // DTW of some candidate is a valid (never too small) best-so-far.
 template <bool FROM_KEYS>
 __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, int64_t ldS, int64_t cstart, int64_t N,
@@ -382,20 +382,23 @@ __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, in
     float *row = S1 + q * ldS;
     unsigned long long top[4] = {kNoKey, kNoKey, kNoKey, kNoKey};
     const int64_t count = FROM_KEYS ? nw : N - cstart;
-    // Thread t takes entries t, t + 256, t + 512, ...; eight of them are loaded before the first
-    // is inserted, so a pass waits for memory once per eight loads.
+    // Thread t takes a contiguous range of entries, so that keys of equal value sit in the block's
+    // key list in the order of their entries (below); eight are loaded before the first is
+    // inserted, so a pass waits for memory once per eight loads.
     constexpr int U = 8;
-    for (int64_t c0 = threadIdx.x; c0 < count; c0 += 256 * U) {
+    const int64_t per = (count + 255) / 256;
+    const int64_t e0 = threadIdx.x * per, e1 = e0 + per < count ? e0 + per : count;
+    for (int64_t c0 = e0; c0 < e1; c0 += U) {
         unsigned long long kk[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t c = c0 + u * 256;
-            const int64_t cc = c < count ? c : count - 1;
+            const int64_t c = c0 + u;
+            const int64_t cc = c < e1 ? c : e1 - 1;
             const unsigned long long k =
                 FROM_KEYS ? wmin[q * nw + cc]
                           : ((unsigned long long)__float_as_uint(row[cstart + cc]) << 32) |
                                 (unsigned long long)(cstart + cc);
-            kk[u] = c < count ? k : kNoKey;
+            kk[u] = c < e1 ? k : kNoKey;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -434,8 +437,10 @@ __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, in
         for (int j = 0; j < 16; ++j) below += __popcll(__ballot(hv[j] < cand));
         if (below < S) T = cand;
     }
-    // every key below T, then keys equal to T in position order until there are S (the 1024 keys
-    // hold at least S at or below T, so exactly S are written)
+    // every key below T, then keys at T in list order until there are S: each thread's keys are
+    // sorted and cover a contiguous range of entries, so equal values go to the earlier entry
+    // (the smaller candidate index for the minima of the pass-0 scans and for S1 rows); the 1024
+    // keys hold at least S at or below T, so exactly S are written
     int nlt = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) nlt += __popcll(__ballot(hv[j] < T));
@@ -446,8 +451,8 @@ __global__ __launch_bounds__(256) void k_select_seeds(float *__restrict__ S1, in
         const unsigned long long mlt = __ballot(hv[j] < T), meq = __ballot(hv[j] == T);
         int r = -1;
         if (hv[j] < T) r = lt + __popcll(mlt & lower);
-        else if (hv[j] == T && eq + __popcll(meq & lower) < S - nlt) r = nlt + eq + __popcll(meq & lower);
-        if (r >= 0) {
+        else if (hv[j] == T) r = nlt + eq + __popcll(meq & lower);
+        if (r >= 0 && r < S) {
             const int c = kv[j] == kNoKey ? -1 : (int)(kv[j] & 0xffffffffu);
             seeds[q * S + r] = c;
             if (c >= 0) row[c] = kInf;  // its DTW is computed by the seeding stage
