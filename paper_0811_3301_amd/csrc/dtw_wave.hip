@@ -27,11 +27,15 @@ namespace lbimp {
 // so min over both cells of all lanes bounds the result.
 constexpr int kWavePad = 96;  // LDS padding of x and y on each side: |i - t|, |j - t| <= 64, +9 read ahead
 
-__device__ __forceinline__ float dpp_shr1(float v) {  // lane l gets lane l-1, lane 0 gets +inf
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(kInf), __float_as_int(v), 0x138, 0xf, 0xf, false));
+// Lane shifts across the wave.  The lane without a source (lane 0 shifting right, lane 63
+// shifting left) keeps `keep`: the callers pass the shift's previous result, whose value in that
+// lane is the +inf it was set to before the first step, so no step spends an instruction
+// refilling it.
+__device__ __forceinline__ float dpp_shr1(float keep, float v) {  // lane l gets lane l-1
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(keep), __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
-__device__ __forceinline__ float dpp_shl1(float v) {  // lane l gets lane l+1, lane 63 gets +inf
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(kInf), __float_as_int(v), 0x130, 0xf, 0xf, false));
+__device__ __forceinline__ float dpp_shl1(float keep, float v) {  // lane l gets lane l+1
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(keep), __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
 template <int P>
@@ -97,11 +101,12 @@ __global__ __launch_bounds__(64) void k_dtw_wavereg(DtwArgs a, int w, int LP) {
         const float *xp = xg + kWavePad + i0;
         const float *yp = ys + kWavePad + j0;
         bool alive = active0;
+        float left = kInf, up = kInf;  // the shifted neighbours; +inf in lanes 0 and 63 throughout
         auto step = [&](float xi, float yj, float yj1) {
-            const float left = dpp_shr1(O);
+            left = dpp_shr1(left, O);
             float Ee = cost_add<P>(xi - yj, __builtin_fminf(__builtin_fminf(left, O), E));
             Ee = e_ok ? Ee : kInf;
-            const float up = dpp_shl1(Ee);
+            up = dpp_shl1(up, Ee);
             float Oo = cost_add<P>(xi - yj1, __builtin_fminf(__builtin_fminf(Ee, up), O));
             O = o_ok ? Oo : kInf;
             E = Ee;
@@ -186,6 +191,7 @@ __global__ __launch_bounds__(64) void k_dtw_wavereg_r(DtwArgs a, int w) {
             O[r] = (here && slot_odd) ? 0.f : kInf;
         }
         bool alive = true;
+        float left0 = kInf, upl = kInf;  // the shifted neighbours; +inf in lanes 0 and 63 throughout
         // steps t0..t0+nb-1 from windows xw[k] = xs[xb + t0 + k], yw[k] = ys[yb + t0 + k]
         auto block = [&](int t0, int nb) {
             float xw[R + 7], yw[R + 8];
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(64) void k_dtw_wavereg_r(DtwArgs a, int w) {
 #pragma unroll
             for (int st = 0; st < 8; ++st) {
                 if (st < nb) {
-                    const float left0 = dpp_shr1(O[R - 1]);
+                    left0 = dpp_shr1(left0, O[R - 1]);
 #pragma unroll
                     for (int r = R - 1; r >= 0; --r) {  // descending: O[r-1] still holds the previous step
                         const float left = (r == 0) ? left0 : O[r - 1];
@@ -204,7 +210,7 @@ __global__ __launch_bounds__(64) void k_dtw_wavereg_r(DtwArgs a, int w) {
                         const float v = cost_add<P>(xw[R - 1 - r + st] - yw[r + st], m);
                         E[r] = 2 * (lane * R + r) <= 2 * w ? v : kInf;
                     }
-                    const float upl = dpp_shl1(E[0]);
+                    upl = dpp_shl1(upl, E[0]);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const float up = (r + 1 < R) ? E[r + 1] : upl;
