@@ -276,7 +276,7 @@ static void chunk_dims(const SearchSpec &sp, int64_t C, SearchDims &d) {
     // one bucket's rows stay in an XCD's L2 while the pairs of every query read them
     const int64_t span = compact_wave_span();
     d.bs = std::max<int64_t>(span, ((int64_t)(2 << 20) / (4 * (int64_t)d.n)) / span * span);
-    d.nb = (d.improved && sp.kn.lbi_buckets && d.C > d.bs && !d.fine) ? (int)((d.C + d.bs - 1) / d.bs) : 1;
+    d.nb = (d.improved && sp.kn.lbi_buckets && d.C > d.bs) ? (int)((d.C + d.bs - 1) / d.bs) : 1;
     // row phases: the second starts at half the series (a multiple of the kernel's row group);
     // the pool holds up to a quarter of the chunk's pairs, at most the context's bound
     const int lr = lane_rows(d.wb);
@@ -482,12 +482,18 @@ static int enqueue_search(lbimp_ctx *ctx, const SearchSpec &sp, const SearchDims
                 // the pass-0 survivors go straight to LB_Improved, which computes their LB_Keogh
                 // (pass 1) from the same read of each row: cnt0 counts the pass-0 survivors, cnt1
                 // those whose LB_Keogh stays below the threshold, cnt2 those of LB_Improved
-                HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt0, s, c0));
+                PairList l0{b.list1, d.C, cnt0, 0};
+                if (d.nb > 1) {  // bucketed by candidate range (XCD-local row reuse in LB_Improved)
+                    HIPTRY(launch_fill_i32(b.cntb, 0, Q * d.nb, s));
+                    HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt0, s, c0, d.bs, b.cntb));
+                    l0 = PairList{b.list1, d.C, b.cntb, 0, 0, d.nb, d.bs, Q};
+                } else {
+                    HIPTRY(launch_compact(S1v, d.Np, c1, Q, T, b.list1, d.C, cnt0, s, c0));
+                }
                 stage_first(5);
-                HIPTRY(launch_items_prefix(cnt0, 0, Q, d.WL, b.prefix, s));
-                HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, PairList{b.list1, d.C, cnt0, 0}, S1v,
-                                  d.Np, b.prefix, Q, nullptr, grid, T, b.list2, d.C, cnt2, nullptr, 1, false, s,
-                                  true, cnt1, S1v));
+                HIPTRY(launch_items_prefix(l0.cnt, 0, Q * d.nb, d.WL, b.prefix, s));
+                HIPTRY(launch_lbi(p, db->rows, (int64_t)N * n * 4, n, wb, qd, l0, S1v, d.Np, b.prefix, Q, nullptr,
+                                  grid, T, b.list2, d.C, cnt2, nullptr, 1, false, s, true, cnt1, S1v));
                 dl = PairList{b.list2, d.C, cnt2, 0};
             } else {
                 if (d.pd) {

@@ -372,21 +372,26 @@ def test_nn_search_lbi_abandon(L, ctx, n, w, p, k):
 @pytest.mark.parametrize("n,w,N", [(128, 13, 9000), (256, 26, 9000), (64, 6, 20000), (300, 80, 9000), (512, 51, 9000),
                                    (2300, 600, 4200)])
 @pytest.mark.parametrize("p,k", [(1, 1), (2, 3), (INF, 2)])
-def test_nn_search_lbi_buckets(L, ctx, n, w, N, p, k):
+@pytest.mark.parametrize("pd", [0, 2])
+def test_nn_search_lbi_buckets(L, ctx, n, w, N, p, k, pd):
     """LB_Improved over survivor lists bucketed by candidate range (walked bucket by bucket, one
-    XCD per bucket): the same pairs are bounded, so answers and every pruning count equal those
-    of the plain lists, bit for bit; the database spans several buckets of each shape."""
-    _say(f"nn_search lbi_buckets n={n} w={w} N={N} p={p} k={k}")
+    XCD per bucket), after the LB_Keogh sweep (pd 0) or fused with LB_Keogh after pass 0 on the
+    32-part cover (pd 2, where the shape allows it): the same pairs are bounded, so answers and
+    every pruning count equal those of the plain lists, bit for bit; the database spans several
+    buckets of each shape."""
+    _say(f"nn_search lbi_buckets n={n} w={w} N={N} p={p} k={k} pd={pd}")
     X = walks(N, n, 38)
     Ys = walks(11, n, 39)
     db = L.Db(ctx, to_dev(X))
     Yd = to_dev(Ys)
-    ri, rd, rst = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
-    L.lbimp_ctx_set_option(ctx, "lbi_buckets", 1)
+    L.lbimp_ctx_set_option(ctx, "pd_prefilter", pd)
     try:
+        ri, rd, rst = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
+        L.lbimp_ctx_set_option(ctx, "lbi_buckets", 1)
         idx, dist, st = L.lbimp_nn_search(ctx, db, Yd, w, p, k, "improved")
     finally:
         L.lbimp_ctx_set_option(ctx, "lbi_buckets", 0)
+        L.lbimp_ctx_set_option(ctx, "pd_prefilter", 0)
     assert torch.equal(idx, ri) and torch.equal(dist, rd)
     assert np.array_equal(st[:, :5], rst[:, :5]) and np.array_equal(st[:, 6], rst[:, 6])
     m = 3 if n <= 512 else 0  # the wide case is checked against the plain lists only
