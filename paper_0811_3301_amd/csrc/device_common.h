@@ -20,6 +20,11 @@ __device__ __forceinline__ u64 make_key(float v, int c) {
 // blocks are dealt to the 8 XCDs in turn (block g on XCD g % 8), so XCD x takes buckets x,
 // x + 8, x + 16, ... and its blocks stride through the items of one bucket before the next;
 // bk names the bucket of the last item.
+// Contiguous form (lists that are not bucketed, on request): block g takes the items
+// [g * total / grid, (g + 1) * total / grid) in order, so it finds its first query once and then
+// steps to the next query when the current one's items are done.  Short items (a few
+// microseconds each) then do not pay a dependent search of the prefix per item, and a block's
+// consecutive items mostly share a query.
 struct ItemCursor {
     long long next, stride, total;
     long long ipq;  // items per query when every query has the same pair count, else 0
@@ -27,8 +32,13 @@ struct ItemCursor {
     int64_t Q;
     int nb, bstep;
     int bk = 0;
+    bool contig = false;
+    long long end = 0;           // contiguous: one past the block's last item
+    int64_t cq = 0;              // contiguous: query of the next item
+    long long qlo = 0, qhi = 0;  // contiguous: items of query cq are [qlo, qhi)
 
-    __device__ ItemCursor(const PairList &pl, const long long *prefix_, int64_t Q_, int batch)
+    __device__ ItemCursor(const PairList &pl, const long long *prefix_, int64_t Q_, int batch,
+                          bool contiguous = false)
         : next(blockIdx.x), stride(gridDim.x), prefix(prefix_), Q(Q_), nb(pl.nb), bstep(1) {
         if (!pl.cnt) {
             ipq = (pl.fixed + batch - 1) / batch;
@@ -44,6 +54,15 @@ struct ItemCursor {
             bstep = 8;
         } else if (nb > 1) {
             bk = 0;
+        } else if (contiguous) {
+            contig = true;
+            next = total * (long long)blockIdx.x / (long long)gridDim.x;
+            end = total * ((long long)blockIdx.x + 1) / (long long)gridDim.x;
+            if (next < end) {
+                cq = ipq ? next / ipq : slot_of(next, 0, Q);
+                qlo = ipq ? cq * ipq : prefix[cq];
+                qhi = ipq ? qlo + ipq : prefix[cq + 1];
+            }
         }
     }
 
@@ -60,6 +79,18 @@ struct ItemCursor {
     }
 
     __device__ bool get(int64_t &q, long long &b) {
+        if (contig) {
+            if (next >= end) return false;
+            while (next >= qhi) {  // the next query with items (qhi reaches total by query Q - 1)
+                ++cq;
+                qlo = qhi;
+                qhi = ipq ? qlo + ipq : prefix[cq + 1];
+            }
+            q = cq;
+            b = next - qlo;
+            ++next;
+            return true;
+        }
         if (nb > 1) {  // next is the item offset within bucket bk
             while (bk < nb) {
                 const long long lo = prefix[(int64_t)bk * Q], range = prefix[(int64_t)(bk + 1) * Q] - lo;

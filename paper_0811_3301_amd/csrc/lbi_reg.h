@@ -187,7 +187,7 @@ __global__ __launch_bounds__(64) void k_lbi_reg(LbiArgs a) {
     int64_t cur_q = -1;
     int64_t q;
     long long b;
-    ItemCursor items(a.pl, a.prefix, a.Q, 64);
+    ItemCursor items(a.pl, a.prefix, a.Q, 64, true);  // contiguous: few query changes per block
     while (items.get(q, b)) {
         if (q != cur_q) {
             __syncthreads();
